@@ -1,0 +1,196 @@
+"""Benchmark: DoF-updates/s of the ADER-DG step on 3D Euler N=4, 81^3 cells.
+
+One "step" = the whole hot path on one batch: adg_predict (predictor,
+extrapolation, volume term), adg_correct (Rusanov, face lift, update, wave
+speeds) and adg_cfl_dt (device-side dt for the next step), on the headline
+workload: 3D compressible Euler, gamma = 1.4, N = 4 (5^3 Gauss-Legendre nodes
+per cell), 81^3 periodic cells on [0,1]^3, density 1 + 0.1 exp(-r^2/0.02),
+u = 0, p = 1, Rusanov flux, dt = 0.9 h / (3 (2N+1) lambda_max) recomputed on
+the device every step.  Inputs are synthetic and resident in HBM before the
+timed region.
+
+Prints ONE JSON line.  Besides the float64 path (``value``) it times the
+mixed-precision path (float predictor, float64 corrector) on the same
+workload and reports its per-field relative L2 difference to the float64
+path after the same number of steps.
+"""
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoF-updates/s, 3D Euler N=4: FP64 vs mixed-precision at stated L2 error"
+FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3     # published vector fp32 (packed); this path issues unpacked FMAs
+
+
+def pred_flops_per_cell(d, n, m, R, cF):
+    """Algorithmic flops of one adg_predict per cell (sum-factorised method):
+    R Picard iterations [d+1 contractions of n x n along one axis over the
+    m n^(d+1) space-time values, d fluxes at n^(d+1) nodes, axis sums and the
+    update], then the final fluxes, time averages, volume contraction,
+    face extrapolations and Q~ = u + dt V."""
+    pic = 2 * (d + 1) * m * n ** (d + 2) + cF * n ** (d + 1) + (d + 2) * m * n ** (d + 1)
+    fin = (cF * n ** (d + 1) + 2 * (d + 1) * m * n ** (d + 1) + 2 * d * m * n ** (d + 1)
+           + 8 * d * m * n ** d + 2 * m * n ** d)
+    return R * pic + fin
+
+
+def corr_bytes_per_cell(d, n, m, real_bytes):
+    """Algorithmic HBM bytes of one adg_correct per cell: read Q~ and write Q
+    (2 m n^d float64), read the cell's own 2d face traces and the 2d
+    neighbour traces once each (2 x 2d x 2 x m n^(d-1) values)."""
+    return 2 * m * n ** d * 8 + 2 * 2 * d * 2 * m * n ** (d - 1) * real_bytes
+
+
+def cpu_baseline(args):
+    """The oracle, untuned, on a bounded sample of the same workload."""
+    import torch
+    from oracle import step as ostep
+    from paper_1801_08682_amd import inputs
+    k = args.cpu_cells
+    wl = inputs.Workload("sample", inputs.EULER, 3, 4, (k, k, k), k / 81.0, (1.4,),
+                         extra={"ic": "bump"})
+    Q = torch.tensor(inputs.initial_state(wl))
+    s = ostep.Setup(wl.pde, 3, 4, wl.n_cells, wl.h, wl.pde_param)
+    dt = ostep.cfl_dt(ostep.max_wave_speed(Q, None, s), 0.9, s)
+    Q = ostep.step(Q, None, dt, s)               # warm-up
+    t0 = time.perf_counter()
+    for _ in range(args.cpu_steps):
+        dt = ostep.cfl_dt(ostep.max_wave_speed(Q, None, s), 0.9, s)
+        Q = ostep.step(Q, None, dt, s)
+    t = time.perf_counter() - t0
+    return {"value": wl.ncells * wl.dofs_per_cell * args.cpu_steps / t,
+            "unit": "DoF-updates/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{k}^3-cell periodic grid of the same workload (Euler N=4, "
+                      f"h=1/81, bump), {args.cpu_steps} steps after 1 warm-up, "
+                      f"torch CPU float64 on {platform.processor() or 'host'}"}
+
+
+def run_path(st, Q0, steps, warmup, cfl, torch):
+    """Warm-up on a copy, then `steps` timed steps; per-kernel event times."""
+    Q = Q0.clone()
+    dtt = st.scalar()
+    st.wave_speed(Q, None)
+    st.cfl_dt(cfl, None, dtt)
+    for _ in range(warmup):
+        st.step(Q, None, dtt)
+        st.cfl_dt(cfl, None, dtt)
+    Q.copy_(Q0)
+    st.wave_speed(Q, None)
+    st.cfl_dt(cfl, None, dtt)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    stream = st.stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for k in range(steps):
+            ev[k][0].record(stream)
+            st.predict(Q, None, dtt)
+            ev[k][1].record(stream)
+            st.correct(Q, None, dtt)
+            ev[k][2].record(stream)
+            st.cfl_dt(cfl, None, dtt)
+            ev[k][3].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pred = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    corr = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    dtk = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+    return Q, wall, pred, corr, dtk
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cells", type=int, default=81)
+    ap.add_argument("--cpu-cells", type=int, default=15)
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU sharding is "
+              "described in DESIGN.md but not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1801_08682_amd import inputs
+    from paper_1801_08682_amd.stepper import Stepper
+
+    wl = inputs.preset("C2").with_(n_cells=(args.cells,) * 3,
+                                   length=args.cells / 81.0)
+    d, n, m = wl.dim, wl.n, wl.m
+    print(f"[bench] building inputs {wl.n_cells} N={wl.order}", file=sys.stderr, flush=True)
+    Q0 = torch.tensor(inputs.initial_state(wl), device="cuda")
+    st = Stepper(wl)
+    print("[bench] fp64 run", file=sys.stderr, flush=True)
+    Q64, wall, pred, corr, dtk = run_path(st, Q0, args.steps, args.warmup, wl.cfl, torch)
+    ms = wall * 1e3 / args.steps
+    dofs = wl.ncells * wl.dofs_per_cell
+    R = wl.order + 1
+    fpc = pred_flops_per_cell(d, n, m, R, 30)
+    achieved = fpc * wl.ncells / (pred * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": dofs * args.steps / wall, "unit": "DoF-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D compressible Euler N=4, {args.cells}^3 periodic cells "
+                               "on [0,1]^3, Gaussian density bump, Rusanov, CFL 0.9/(2N+1), "
+                               "dt recomputed on device each step",
+                   "cells": wl.ncells, "dofs_per_cell": wl.dofs_per_cell,
+                   "picard_iters": R, "precision": "fp64"},
+        "kernel_ms": {"predict": pred, "correct": corr, "cfl_dt": dtk},
+        "cell_updates_per_s": wl.ncells * args.steps / wall,
+        "roofline": {"kernel": "k_pred (adg_predict)", "bound": "alu", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_cell": fpc},
+        "correct_hbm": {"achieved_GBps": corr_bytes_per_cell(d, n, m, 8) * wl.ncells
+                        / (corr * 1e-3) / 1e9, "peak_GBps": 8000.0},
+    }
+    st.close()
+    del st
+    if not args.no_mixed:
+        print("[bench] fp32-predictor run", file=sys.stderr, flush=True)
+        st32 = Stepper(wl.with_(precision=inputs.FP32))
+        Q32, wall32, pred32, corr32, dtk32 = run_path(st32, Q0, args.steps, args.warmup,
+                                                     wl.cfl, torch)
+        W = torch.tensor(np.kron(np.kron(st32_w(n), st32_w(n)), st32_w(n)), device="cuda")
+        err = []
+        for v in range(m):
+            e = torch.sqrt((W * (Q32[..., v] - Q64[..., v]) ** 2).sum())
+            r = torch.sqrt((W * Q64[..., v] ** 2).sum())
+            err.append(float(e / r) if float(r) > 1e-8 * float(torch.sqrt((W * Q64[..., 0] ** 2).sum())) else float(e))
+        out["mixed"] = {"precision": "fp32 predictor, fp64 corrector",
+                        "value": dofs * args.steps / wall32, "ms_per_step": wall32 * 1e3 / args.steps,
+                        "kernel_ms": {"predict": pred32, "correct": corr32, "cfl_dt": dtk32},
+                        "rel_l2_vs_fp64_per_field": err,
+                        "l2_note": f"after {args.steps} steps, against the float64 GPU path "
+                                   "(parity-checked against the oracle); absolute L2 for "
+                                   "fields with negligible norm (momentum)"}
+        st32.close()
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+def st32_w(n):
+    z, om = np.polynomial.legendre.leggauss(n)
+    return 0.5 * om
+
+
+if __name__ == "__main__":
+    main()

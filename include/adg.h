@@ -1,0 +1,153 @@
+/*
+ * adg.h -- C ABI of the MI355X (gfx950) ADER-DG step library, libadg.so.
+ *
+ * One explicit ADER-DG time step on a uniform periodic Cartesian grid, as
+ * defined in Charrier & Weinzierl, "Stop talking to me -- a
+ * communication-avoiding ADER-DG realisation" (arXiv:1801.08682):
+ *   Sec. 3, Eq. (5)/(6):  Q(T + dT) = (id + (integrateVolume + integrateFace
+ *                         o solveRiemann o extrapolate) o predict) Q(T),
+ * with predict evaluated once per cell (Sec. 4, Constraint 1) and only the
+ * face hull of the space-time predictor kept (Sec. 4, Theorem 1).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Every argument named d_* is a DEVICE pointer owned by the caller; the
+ *    library never allocates or frees device memory after adg_init and never
+ *    frees caller memory.  Device buffers must be 16-byte aligned.
+ *  - Layouts (float64, contiguous):
+ *      Q[cell][node][var]   cell = ix + nx*(iy + ny*iz), node = kx + n*(ky + n*kz)
+ *                           with n = order + 1 Gauss-Legendre points per axis,
+ *                           var innermost (m variables).
+ *      params[cell][k]      per-cell material: acoustics (c), elasticity
+ *                           (rho, lambda, mu); none for advection and Euler.
+ *  - Calls are asynchronous: they enqueue kernels on the stream given to
+ *    adg_init and return.  Numerical failures (non-finite values, rho <= 0 or
+ *    p <= 0 for Euler) surface only through the device flag of adg_step.
+ *  - A context is not thread-safe: one context per stream.  Calls that overlap
+ *    on the same context race on its workspace.
+ *  - Errors: a status code is returned; no exceptions or aborts cross the ABI.
+ *    ADG_ERR_INVALID_ARG  null required pointer, misaligned buffer, bad
+ *                         dimension/order/cell count, non-uniform h, bad PDE;
+ *    ADG_ERR_UNSUPPORTED  valid combination of (dim, order, pde, precision)
+ *                         that is not compiled into this library;
+ *    ADG_ERR_WORKSPACE    workspace smaller than adg_query reported;
+ *    ADG_ERR_DEVICE       a HIP launch or runtime error; adg_last_error()
+ *                         gives the message.
+ */
+#ifndef ADG_H_
+#define ADG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADG_OK = 0,
+  ADG_ERR_INVALID_ARG = 1,
+  ADG_ERR_UNSUPPORTED = 2,
+  ADG_ERR_DEVICE = 3,
+  ADG_ERR_WORKSPACE = 4
+} adg_status;
+
+/* PDE of Eq. (1) with B_i = 0, S = 0 (Sec. 3); m = number of variables.
+ *  ADVECTION  m = 1, pde_param = velocity (a_1..a_d)
+ *  EULER      m = d + 2, Q = (rho, j, E), pde_param[0] = gamma (Sec. 7)
+ *  ELASTIC    m = d + 6 (3D) / d + 3 (2D), Q = (v, Voigt stresses),
+ *             params per cell (rho, lambda, mu)
+ *  ACOUSTIC   m = d + 1, Q = (p, u), params per cell (c) */
+typedef enum { ADG_ADVECTION = 0, ADG_EULER = 1, ADG_ELASTIC = 2, ADG_ACOUSTIC = 3 } adg_pde;
+
+/* Arithmetic of the predictor (predict + extrapolate).  The volume
+ * integration, Riemann solve, face integration and update always run in
+ * float64.  FP32: float Picard iteration and float face traces. */
+typedef enum { ADG_FP64 = 0, ADG_FP32 = 1, ADG_BF16 = 2 } adg_precision;
+
+typedef struct {
+  int32_t dim;            /* d in {2, 3} */
+  int32_t order;          /* N (the paper's p); n = N + 1 nodes per axis */
+  int32_t n_cells[3];     /* periodic grid; n_cells[2] ignored when dim == 2 */
+  double length[3];       /* domain edge lengths; h = length[i]/n_cells[i] must agree */
+  int32_t pde;            /* adg_pde */
+  double pde_param[4];    /* see adg_pde */
+  int32_t picard_iters;   /* R; 0 selects N + 1 */
+  int32_t precision;      /* adg_precision */
+} adg_config;
+
+typedef struct adg_ctx adg_ctx;
+
+/* Sizes for a configuration; host-only, needs no GPU.
+ *   dofs_per_cell   = m (N+1)^d   (Sec. 3: m (p+1)^d coefficients per cell)
+ *   params_per_cell = per-cell material count (0, 1 or 3)
+ *   workspace_bytes = device workspace the caller must pass to adg_init: the
+ *                     time-integrated face hull (Theorem 1; Table 1 task
+ *                     extrapolate, reduced to one time value per face node)
+ *                     plus reduction scratch.
+ * Any output pointer may be NULL.  Returns INVALID_ARG / UNSUPPORTED as above. */
+adg_status adg_query(const adg_config* cfg, int64_t* dofs_per_cell, int64_t* params_per_cell,
+                     int64_t* workspace_bytes);
+
+/* Create a context bound to `stream` (a hipStream_t; NULL = default stream)
+ * and to the caller-owned workspace d_workspace of workspace_bytes bytes.
+ * Builds the 1D Gauss-Legendre operators on the host.  *out receives the
+ * context (host memory owned by the library; free with adg_destroy). */
+adg_status adg_init(const adg_config* cfg, void* d_workspace, int64_t workspace_bytes, void* stream,
+                    adg_ctx** out);
+
+/* STP step (Sec. 3 "ADER-DG step 1", Eq. (3); Table 1 predict + extrapolate)
+ * with integrateVolume brought forward (Sec. 5, Technique 1):
+ * for every cell, Picard-iterate the space-time predictor with time step
+ * *d_dt, write the time-integrated face traces into the workspace and
+ * overwrite Q in place with Q~ = Q + dt * (volume term of Eq. (2)).
+ * d_params may be NULL when the PDE has no per-cell parameters. */
+adg_status adg_predict(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt);
+
+/* Riemann + Corrector (Sec. 3 "ADER-DG steps 2 and 3"; Eq. (4) Rusanov;
+ * Table 1 solveRiemann, integrateFace, update, calcTimeStep): for every cell
+ * solve the Rusanov problems of its 2d faces from the traces written by
+ * adg_predict, add the face term of Eq. (2) to Q~ in place, and record the
+ * per-block maximum wave speed of the new state for adg_cfl_dt.
+ * d_flag (nullable) is OR-ed with 1 on a non-finite state and 2 on a
+ * non-physical one; the caller zeroes it. */
+adg_status adg_correct(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt,
+                       int32_t* d_flag);
+
+/* One full time step, Alg. 1 (left) without the time-step update:
+ * adg_predict followed by adg_correct.  Q(T) -> Q(T + dt) in place. */
+adg_status adg_step(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt,
+                    int32_t* d_flag);
+
+/* Record the per-block maximum directional wave speed of Q (as adg_correct
+ * does for the new state), e.g. before the first step. */
+adg_status adg_wave_speed(adg_ctx* ctx, const double* d_Q, const double* d_params);
+
+/* calcTimeStep and the global reduction (Sec. 3 "Time stepping"; Alg. 1):
+ * reduce the per-block maxima recorded by the last adg_correct or
+ * adg_wave_speed into *d_lambda_max (nullable) and set, on the device,
+ * *d_dt = cfl * h / (d (2N + 1) lambda_max).  No host synchronisation. */
+adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_dt);
+
+/* Reverse mode of one adg_step with dt held fixed (the discrete adjoint of
+ * Eq. (5)/(6) including the Picard iterations and the Rusanov maximum):
+ *   d_Qbar (in)  dJ/dQ(T + dt), (out) dJ/dQ(T), in place;
+ *   d_params_bar (nullable) += dJ/dparams.
+ * d_Qn is Q(T) and is not modified.  Uses the workspace. */
+adg_status adg_step_adjoint(adg_ctx* ctx, const double* d_Qn, const double* d_params,
+                            const double* d_dt, double* d_Qbar, double* d_params_bar);
+
+/* Free a context (host memory only). */
+adg_status adg_destroy(adg_ctx* ctx);
+
+/* Last error message of a context ("" if none); ctx may be NULL for errors of
+ * adg_query/adg_init.  The string is valid until the next call. */
+const char* adg_last_error(const adg_ctx* ctx);
+
+/* Library version, (major << 16) | minor. */
+int32_t adg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADG_H_ */

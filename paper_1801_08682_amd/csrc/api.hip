@@ -1,0 +1,301 @@
+// C ABI of libadg.so (declared in include/adg.h): validation, workspace
+// layout, the 1D operator tables and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/adg.h"
+#include "common.hpp"
+#include "kernels_fwd.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Layout {
+  int64_t trace_off = 0, trace_bytes = 0;
+  int64_t partial_off = 0, partial_count = 0;
+  int64_t scratch_off = 0, scratch_bytes = 0;
+  int64_t total = 0;
+};
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+int n_vars(int pde, int dim) {
+  switch (pde) {
+    case ADG_ADVECTION: return 1;
+    case ADG_EULER: return dim + 2;
+    case ADG_ACOUSTIC: return dim + 1;
+    case ADG_ELASTIC: return dim + (dim == 3 ? 6 : 3);
+  }
+  return 0;
+}
+
+int n_params(int pde) {
+  return pde == ADG_ACOUSTIC ? 1 : (pde == ADG_ELASTIC ? 3 : 0);
+}
+
+adg_status validate(const adg_config* c, std::string* msg) {
+  if (!c) { *msg = "config is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (c->dim != 2 && c->dim != 3) { *msg = "dim must be 2 or 3"; return ADG_ERR_INVALID_ARG; }
+  if (c->order < 0 || c->order > 15) { *msg = "order must be in [0, 15]"; return ADG_ERR_INVALID_ARG; }
+  if (c->pde < 0 || c->pde > 3) { *msg = "unknown pde"; return ADG_ERR_INVALID_ARG; }
+  if (c->precision < 0 || c->precision > 2) { *msg = "unknown precision"; return ADG_ERR_INVALID_ARG; }
+  if (c->picard_iters < 0 || c->picard_iters > 1000) {
+    *msg = "picard_iters must be in [0, 1000]";
+    return ADG_ERR_INVALID_ARG;
+  }
+  double h0 = 0.0;
+  int64_t cells = 1;
+  for (int i = 0; i < c->dim; ++i) {
+    if (c->n_cells[i] < 1) { *msg = "n_cells must be >= 1"; return ADG_ERR_INVALID_ARG; }
+    if (!(c->length[i] > 0.0) || !std::isfinite(c->length[i])) {
+      *msg = "length must be positive";
+      return ADG_ERR_INVALID_ARG;
+    }
+    const double h = c->length[i] / c->n_cells[i];
+    if (i == 0) h0 = h;
+    else if (std::fabs(h - h0) > 1e-12 * h0) { *msg = "cell width must be uniform"; return ADG_ERR_INVALID_ARG; }
+    cells *= c->n_cells[i];
+  }
+  if (cells > (int64_t(1) << 31)) { *msg = "too many cells"; return ADG_ERR_INVALID_ARG; }
+  if (c->pde == ADG_EULER) {
+    const double g = c->pde_param[0] == 0.0 ? 1.4 : c->pde_param[0];
+    if (!(g > 1.0)) { *msg = "Euler needs gamma > 1"; return ADG_ERR_INVALID_ARG; }
+  }
+  return ADG_OK;
+}
+
+const adg::Launchers* find(const adg_config* c) {
+  switch (c->pde) {
+    case ADG_ADVECTION: return adg::find_advection(c->dim, c->order, c->precision);
+    case ADG_EULER: return adg::find_euler(c->dim, c->order, c->precision);
+    case ADG_ACOUSTIC: return adg::find_acoustic(c->dim, c->order, c->precision);
+    case ADG_ELASTIC: return adg::find_elastic(c->dim, c->order, c->precision);
+  }
+  return nullptr;
+}
+
+int64_t n_cells_of(const adg_config* c) {
+  int64_t k = 1;
+  for (int i = 0; i < c->dim; ++i) k *= c->n_cells[i];
+  return k;
+}
+
+Layout layout_of(const adg_config* c, const adg::Launchers* L) {
+  Layout l;
+  const int64_t cells = n_cells_of(c);
+  l.trace_off = 0;
+  l.trace_bytes = align256(cells * L->trace_bytes_per_cell);
+  l.partial_off = l.trace_off + l.trace_bytes;
+  l.partial_count = adg::kMaxReduceBlocks;
+  l.scratch_off = l.partial_off + align256(l.partial_count * 8);
+  l.scratch_bytes = align256(cells * L->scratch_bytes_per_cell);
+  l.total = l.scratch_off + l.scratch_bytes;
+  return l;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+__global__ void __launch_bounds__(256) k_dt(const double* partial, int64_t cnt, double coef,
+                                            double* lam_out, double* dt_out) {
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int64_t k = threadIdx.x; k < cnt; k += 256) m = fmax(m, partial[k]);
+  m = adg::block_max<256>(m, red);
+  if (threadIdx.x == 0) {
+    if (lam_out) *lam_out = m;
+    if (dt_out) *dt_out = coef / m;
+  }
+}
+
+}  // namespace
+
+struct adg_ctx {
+  adg_config cfg;
+  const adg::Launchers* L = nullptr;
+  adg::HostTables tab;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout lay;
+  int64_t n_partial_used = 0;
+  int64_t ncells = 0;
+  double h = 1.0;
+  int R = 1;
+  double gp[4] = {0, 0, 0, 0};
+  std::string err;
+
+  adg::LaunchArgs args() {
+    adg::LaunchArgs a;
+    a.traces = ws + lay.trace_off;
+    a.partial = reinterpret_cast<double*>(ws + lay.partial_off);
+    a.n_partial = lay.partial_count;
+    a.n_partial_used = &n_partial_used;
+    a.scratch = ws + lay.scratch_off;
+    a.ncells = ncells;
+    for (int i = 0; i < 3; ++i) a.nc[i] = (i < cfg.dim) ? cfg.n_cells[i] : 1;
+    a.inv_h = 1.0 / h;
+    a.R = R;
+    for (int k = 0; k < 4; ++k) a.gp[k] = gp[k];
+    a.tab = &tab;
+    a.stream = stream;
+    return a;
+  }
+  adg_status fail(adg_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+  adg_status launched(int e, const char* what) {
+    if (e != 0) {
+      err = std::string(what) + ": " + hipGetErrorString((hipError_t)e);
+      return ADG_ERR_DEVICE;
+    }
+    return ADG_OK;
+  }
+};
+
+extern "C" {
+
+int32_t adg_version(void) { return (1 << 16) | 0; }
+
+const char* adg_last_error(const adg_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+adg_status adg_query(const adg_config* cfg, int64_t* dofs_per_cell, int64_t* params_per_cell,
+                     int64_t* workspace_bytes) {
+  std::string msg;
+  adg_status s = validate(cfg, &msg);
+  if (s != ADG_OK) { g_err = msg; return s; }
+  const adg::Launchers* L = find(cfg);
+  if (!L) { g_err = "combination (dim, order, pde, precision) not compiled"; return ADG_ERR_UNSUPPORTED; }
+  int64_t nn = 1;
+  for (int i = 0; i < cfg->dim; ++i) nn *= (cfg->order + 1);
+  if (dofs_per_cell) *dofs_per_cell = nn * n_vars(cfg->pde, cfg->dim);
+  if (params_per_cell) *params_per_cell = n_params(cfg->pde);
+  if (workspace_bytes) *workspace_bytes = layout_of(cfg, L).total;
+  g_err.clear();
+  return ADG_OK;
+}
+
+adg_status adg_init(const adg_config* cfg, void* d_workspace, int64_t workspace_bytes, void* stream,
+                    adg_ctx** out) {
+  if (!out) { g_err = "out is NULL"; return ADG_ERR_INVALID_ARG; }
+  *out = nullptr;
+  int64_t need = 0;
+  adg_status s = adg_query(cfg, nullptr, nullptr, &need);
+  if (s != ADG_OK) return s;
+  if (!d_workspace) { g_err = "workspace is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (!aligned16(d_workspace)) { g_err = "workspace not 16-byte aligned"; return ADG_ERR_INVALID_ARG; }
+  if (workspace_bytes < need) { g_err = "workspace too small"; return ADG_ERR_WORKSPACE; }
+  adg_ctx* c = new adg_ctx();
+  c->cfg = *cfg;
+  c->L = find(cfg);
+  if (!adg::build_tables(cfg->order + 1, &c->tab)) {
+    delete c;
+    g_err = "table construction failed";
+    return ADG_ERR_INVALID_ARG;
+  }
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(d_workspace);
+  c->lay = layout_of(cfg, c->L);
+  c->ncells = n_cells_of(cfg);
+  c->h = cfg->length[0] / cfg->n_cells[0];
+  c->R = cfg->picard_iters > 0 ? cfg->picard_iters : cfg->order + 1;
+  if (cfg->pde == ADG_EULER) {
+    const double g = cfg->pde_param[0] == 0.0 ? 1.4 : cfg->pde_param[0];
+    c->gp[0] = g;
+    c->gp[1] = g - 1.0;
+  } else {
+    for (int k = 0; k < 4; ++k) c->gp[k] = cfg->pde_param[k];
+  }
+  *out = c;
+  g_err.clear();
+  return ADG_OK;
+}
+
+adg_status adg_destroy(adg_ctx* ctx) {
+  delete ctx;
+  return ADG_OK;
+}
+
+static adg_status check_state(adg_ctx* ctx, const void* Q, const void* params, const void* dt) {
+  if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (!Q || !dt) return ctx->fail(ADG_ERR_INVALID_ARG, "Q and dt are required");
+  if (n_params(ctx->cfg.pde) > 0 && !params)
+    return ctx->fail(ADG_ERR_INVALID_ARG, "this PDE needs per-cell params");
+  if (!aligned16(Q) || (params && !aligned16(params)))
+    return ctx->fail(ADG_ERR_INVALID_ARG, "device buffers must be 16-byte aligned");
+  return ADG_OK;
+}
+
+adg_status adg_predict(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt) {
+  adg_status s = check_state(ctx, d_Q, d_params, d_dt);
+  if (s != ADG_OK) return s;
+  adg::LaunchArgs a = ctx->args();
+  a.Q = d_Q;
+  a.params = d_params;
+  a.dt = d_dt;
+  return ctx->launched(ctx->L->predict(a), "predict");
+}
+
+adg_status adg_correct(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt,
+                       int32_t* d_flag) {
+  adg_status s = check_state(ctx, d_Q, d_params, d_dt);
+  if (s != ADG_OK) return s;
+  adg::LaunchArgs a = ctx->args();
+  a.Q = d_Q;
+  a.params = d_params;
+  a.dt = d_dt;
+  a.flag = d_flag;
+  return ctx->launched(ctx->L->correct(a), "correct");
+}
+
+adg_status adg_step(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt,
+                    int32_t* d_flag) {
+  adg_status s = adg_predict(ctx, d_Q, d_params, d_dt);
+  if (s != ADG_OK) return s;
+  return adg_correct(ctx, d_Q, d_params, d_dt, d_flag);
+}
+
+adg_status adg_wave_speed(adg_ctx* ctx, const double* d_Q, const double* d_params) {
+  double one = 1.0;
+  adg_status s = check_state(ctx, d_Q, d_params, &one);
+  if (s != ADG_OK) return s;
+  adg::LaunchArgs a = ctx->args();
+  a.Qc = d_Q;
+  a.params = d_params;
+  return ctx->launched(ctx->L->wave_speed(a), "wave_speed");
+}
+
+adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_dt) {
+  if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (!(cfl > 0.0)) return ctx->fail(ADG_ERR_INVALID_ARG, "cfl must be positive");
+  if (!d_lambda_max && !d_dt) return ctx->fail(ADG_ERR_INVALID_ARG, "no output");
+  if (ctx->n_partial_used <= 0)
+    return ctx->fail(ADG_ERR_INVALID_ARG, "no wave speeds recorded (call adg_correct or adg_wave_speed)");
+  const double coef = cfl * ctx->h / (ctx->cfg.dim * (2.0 * ctx->cfg.order + 1.0));
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream,
+                     reinterpret_cast<const double*>(ctx->ws + ctx->lay.partial_off), ctx->n_partial_used,
+                     coef, d_lambda_max, d_dt);
+  return ctx->launched((int)hipGetLastError(), "cfl_dt");
+}
+
+adg_status adg_step_adjoint(adg_ctx* ctx, const double* d_Qn, const double* d_params, const double* d_dt,
+                            double* d_Qbar, double* d_params_bar) {
+  adg_status s = check_state(ctx, d_Qn, d_params, d_dt);
+  if (s != ADG_OK) return s;
+  if (!d_Qbar) return ctx->fail(ADG_ERR_INVALID_ARG, "Qbar is required");
+  if (!ctx->L->adjoint) return ctx->fail(ADG_ERR_UNSUPPORTED, "adjoint not compiled for this configuration");
+  adg::LaunchArgs a = ctx->args();
+  a.Qc = d_Qn;
+  a.params = d_params;
+  a.dt = d_dt;
+  a.Qbar = d_Qbar;
+  a.params_bar = d_params_bar;
+  return ctx->launched(ctx->L->adjoint(a), "adjoint");
+}
+
+}  // extern "C"

@@ -1,0 +1,12 @@
+// Instantiations of the elastic kernels: 2D orders {1, 2, 3, 4}, 3D orders {1, 2, 3, 4, 5}.
+#include "registry.hpp"
+
+namespace adg {
+
+const Launchers* find_elastic(int dim, int order, int prec) {
+  if (dim == 2) return pick_order<Elastic, 2, 1, 2, 3, 4>(order, prec);
+  if (dim == 3) return pick_order<Elastic, 3, 1, 2, 3, 4, 5>(order, prec);
+  return nullptr;
+}
+
+}  // namespace adg

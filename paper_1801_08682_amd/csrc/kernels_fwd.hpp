@@ -1,0 +1,553 @@
+// Forward kernels of one ADER-DG step for gfx950.
+//
+//  k_pred  predict + extrapolate + integrateVolume     (Sec. 3 step 1, Eq. (3);
+//          Table 1; Sec. 5 Technique 1: volume integral right after predict)
+//  k_corr  solveRiemann (Rusanov, Eq. (4)) + integrateFace + update +
+//          calcTimeStep (Sec. 3 steps 2, 3; Eq. (2))
+//  k_lam   wave-speed maxima of a given state
+//  k_dt    global maximum and dt = C h / (d (2N+1) lambda)   (Sec. 3 "Time stepping")
+//
+// k_pred mapping.  One workgroup holds CPB cells, one thread per spatial node
+// ("node role").  The node thread keeps the time column of its node q[t][v]
+// and the Picard accumulator in registers.  Spatial contractions need a whole
+// pencil along axis i: per batch of S time slices the node threads publish
+// q into LDS, then every thread takes "pencil tasks" (one time slice, one
+// pencil along axis i): it evaluates F_i at the n pencil nodes and contracts
+// with D (n^2 m FMAs from n m LDS reads), summing into an LDS slice buffer.
+// The node thread then applies the time operator P from registers.  The
+// space-time tensor never reaches HBM (Theorem 1): only the 2d face traces
+// (time-integrated) and Q~ = Q + dt V are written.
+#pragma once
+
+#include "common.hpp"
+
+namespace adg {
+
+template <int D_, int N_, template <int> class PDET, class Real_>
+struct Fwd {
+  static constexpr int D = D_, N = N_, n = N_ + 1;
+  using PDE = PDET<D_>;
+  using Real = Real_;
+  static constexpr int M = PDE::M, NPAR = PDE::NPAR;
+  static constexpr int NS = ipow(n, D), NF = ipow(n, D - 1);
+  static constexpr int NQ = PDE::LINEAR ? 1 : 2;
+  // predictor block
+  static constexpr int CPB = (NS >= 128) ? 1 : 128 / NS;
+  static constexpr int THREADS = CPB * NS;
+  static constexpr int LDS_BUDGET = 80 * 1024;
+  static constexpr int SLICE_BYTES = 2 * NS * M * (int)sizeof(Real);
+  static constexpr int pick_S() {
+    for (int s = n; s > 1; --s)
+      if (CPB * s * SLICE_BYTES <= LDS_BUDGET) return s;
+    return 1;
+  }
+  static constexpr int S = pick_S();
+  static constexpr int NB = (n + S - 1) / S;                 // batches per iteration
+  static constexpr int PIC_BYTES = 2 * S * NS * M * (int)sizeof(Real);
+  static constexpr int FIN_BYTES = 3 * NS * M * 8;
+  static constexpr int CELL_BYTES = PIC_BYTES > FIN_BYTES ? PIC_BYTES : FIN_BYTES;
+  static constexpr int LDS_BYTES = CPB * CELL_BYTES;
+  static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
+  static constexpr int64_t TRACE_ELEMS = 2LL * D * NQ * NF * M;   // per cell
+  // corrector block: one thread per face task and per node
+  static constexpr int FT = 2 * D * NF;
+  static constexpr int CT = NS > FT ? NS : FT;
+  static constexpr int CCPB = (CT >= 128) ? 1 : 128 / CT;
+  static constexpr int CTHREADS = CCPB * CT;
+  static constexpr int CORR_CELL_BYTES = (2 * D * NF * (M + 1) + 2 * D) * 8;
+};
+
+template <class K>
+struct PredP {
+  double* Q;
+  const double* par;
+  const double* dt;
+  typename K::Real* tr;
+  int64_t ncells;
+  double inv_h;
+  int R;
+  Gconst<typename K::Real> g;
+  KTab<K::n, typename K::Real> t;
+};
+
+template <class K>
+__global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
+  using Real = typename K::Real;
+  using PDE = typename K::PDE;
+  constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, S = K::S, D = K::D;
+  __shared__ __align__(16) unsigned char smem[K::LDS_BYTES];
+
+  const int lc = threadIdx.x / NS;
+  const int a = threadIdx.x - lc * NS;
+  const int64_t cell = (int64_t)blockIdx.x * K::CPB + lc;
+  const bool live = cell < p.ncells;
+  const int64_t cs = live ? cell : 0;
+  unsigned char* base = smem + lc * K::CELL_BYTES;
+  Real* Qs = reinterpret_cast<Real*>(base);
+  Real* Rs = Qs + S * NS * M;
+
+  const double cdt = (*p.dt) * p.inv_h;   // dt / h
+  const Real c = (Real)cdt;
+  double u[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) u[v] = p.Q[(cs * NS + a) * M + v];
+  const auto cp = PDE::template cell<Real>(p.par + cs * K::NPAR);
+
+  Real q[n][M];
+#pragma unroll
+  for (int t = 0; t < n; ++t)
+#pragma unroll
+    for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v];
+
+  // ---- predict: Picard iteration q <- u - (dt/h) P sum_i D_i F_i(q) ----
+  for (int r = 0; r < p.R; ++r) {
+    Real acc[n][M];
+#pragma unroll
+    for (int t = 0; t < n; ++t)
+#pragma unroll
+      for (int v = 0; v < M; ++v) acc[t][v] = Real(0);
+
+    static_for<0, K::NB>([&](auto B_) {
+      constexpr int t0 = decltype(B_)::value * S;
+      constexpr int ns = (n - t0) < S ? (n - t0) : S;
+#pragma unroll
+      for (int tt = 0; tt < ns; ++tt)
+#pragma unroll
+        for (int v = 0; v < M; ++v) Qs[(tt * M + v) * NS + a] = q[t0 + tt][v];
+      __syncthreads();
+
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        for (int task = a; task < ns * NF; task += NS) {
+          const int tt = task / NF;
+          const int b = task - tt * NF;
+          const Real* qsl = Qs + tt * M * NS;
+          Real out[n][M];
+#pragma unroll
+          for (int k = 0; k < n; ++k)
+#pragma unroll
+            for (int v = 0; v < M; ++v) out[k][v] = Real(0);
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            const int nd = pencil_node<n, I>(b, j);
+            Real qn[M], F[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) qn[v] = qsl[v * NS + nd];
+            PDE::template flux<I>(qn, F, p.g, cp);
+#pragma unroll
+            for (int k = 0; k < n; ++k)
+#pragma unroll
+              for (int v = 0; v < M; ++v) out[k][v] += p.t.D[k][j] * F[v];
+          }
+          Real* rsl = Rs + tt * M * NS;
+#pragma unroll
+          for (int k = 0; k < n; ++k) {
+            const int nd = pencil_node<n, I>(b, k);
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+              if constexpr (I == 0) rsl[v * NS + nd] = out[k][v];
+              else rsl[v * NS + nd] += out[k][v];
+            }
+          }
+        }
+        __syncthreads();
+      });
+
+#pragma unroll
+      for (int tt = 0; tt < ns; ++tt)
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          const Real rv = Rs[(tt * M + v) * NS + a];
+#pragma unroll
+          for (int t = 0; t < n; ++t) acc[t][v] += p.t.P[t][t0 + tt] * rv;
+        }
+      __syncthreads();
+    });
+
+#pragma unroll
+    for (int t = 0; t < n; ++t)
+#pragma unroll
+      for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v] - c * acc[t][v];
+  }
+
+  // ---- extrapolate + integrateVolume on time averages (float64) ----
+  double* Fb = reinterpret_cast<double*>(base);
+  double* Qb = Fb + NS * M;
+  double* Vs = Qb + NS * M;
+  {
+    double qb[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < n; ++t) s += p.t.w[t] * (double)q[t][v];
+      qb[v] = s;
+      Qb[v * NS + a] = s;
+    }
+  }
+  static_for<0, D>([&](auto I_) {
+    constexpr int I = decltype(I_)::value;
+    {
+      double fb[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) fb[v] = 0.0;
+#pragma unroll
+      for (int t = 0; t < n; ++t) {
+        Real F[M];
+        PDE::template flux<I>(q[t], F, p.g, cp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) fb[v] += p.t.w[t] * (double)F[v];
+      }
+#pragma unroll
+      for (int v = 0; v < M; ++v) Fb[v * NS + a] = fb[v];
+    }
+    __syncthreads();
+    for (int b = a; b < NF; b += NS) {
+      double vol[n][M], qL[M], qR[M], fL[M], fR[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        qL[v] = qR[v] = fL[v] = fR[v] = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) vol[k][v] = 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        const int nd = pencil_node<n, I>(b, j);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          const double fv = Fb[v * NS + nd];
+          const double qv = Qb[v * NS + nd];
+#pragma unroll
+          for (int k = 0; k < n; ++k) vol[k][v] += p.t.Kv[k][j] * fv;
+          qL[v] += p.t.FL[j] * qv;
+          qR[v] += p.t.FR[j] * qv;
+          fL[v] += p.t.FL[j] * fv;
+          fR[v] += p.t.FR[j] * fv;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const int nd = pencil_node<n, I>(b, k);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          if constexpr (I == 0) Vs[v * NS + nd] = vol[k][v];
+          else Vs[v * NS + nd] += vol[k][v];
+        }
+      }
+      if (live) {
+        Real* tr = p.tr + cell * K::TRACE_ELEMS;
+        Real* tL = tr + (int64_t)(2 * I) * K::NQ * NF * M + b * M;
+        Real* tR = tr + (int64_t)(2 * I + 1) * K::NQ * NF * M + b * M;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          tL[v] = (Real)qL[v];
+          tR[v] = (Real)qR[v];
+        }
+        if constexpr (K::NQ == 2) {
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            tL[NF * M + v] = (Real)fL[v];
+            tR[NF * M + v] = (Real)fR[v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  });
+  if (live) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) p.Q[(cell * NS + a) * M + v] = u[v] + cdt * Vs[v * NS + a];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide maximum of non-negative doubles; result valid in thread 0.
+template <int THREADS>
+__device__ __forceinline__ double block_max(double x, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  constexpr int NW = (THREADS + 63) / 64;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) r = fmax(r, red[k]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// Cell-group schedule of the reduction kernels: XCD-aware when the grid is a
+// multiple of 8 (workgroup k runs on XCD k mod 8; each XCD walks one
+// contiguous range of cells so neighbour traces are shared in its L2).
+struct GroupIter {
+  int64_t g, end, step;
+  __device__ GroupIter(int64_t groups) {
+    const int64_t G = gridDim.x;
+    if (G % 8 == 0) {
+      const int64_t x = blockIdx.x % 8, k = blockIdx.x / 8, per = G / 8;
+      const int64_t span = (groups + 7) / 8;
+      g = x * span + k;
+      end = min(groups, (x + 1) * span);
+      step = per;
+    } else {
+      g = blockIdx.x;
+      end = groups;
+      step = G;
+    }
+  }
+};
+
+template <class K>
+struct CorrP {
+  double* Q;
+  const double* par;
+  const double* dt;
+  const typename K::Real* tr;
+  double* partial;
+  int32_t* flag;
+  int64_t ncells;
+  int nc[3];
+  double inv_h;
+  Gconst<double> g;
+  double LL[K::n], LR[K::n];
+};
+
+template <class K>
+__device__ __forceinline__ int64_t neighbour(int64_t cell, int i, int dir, const int* nc) {
+  int64_t ix = cell % nc[0];
+  int64_t rest = cell / nc[0];
+  int64_t iy = rest % nc[1];
+  int64_t iz = rest / nc[1];
+  if (i == 0) ix = (ix + dir + nc[0]) % nc[0];
+  else if (i == 1) iy = (iy + dir + nc[1]) % nc[1];
+  else iz = (iz + dir + nc[2]) % nc[2];
+  return ix + nc[0] * (iy + nc[1] * iz);
+}
+
+template <class K>
+__global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
+  using Real = typename K::Real;
+  using PDE = typename K::PDE;
+  constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, CT = K::CT;
+  __shared__ double lds[K::CCPB * K::CORR_CELL_BYTES / 8];
+  __shared__ double red[(K::CTHREADS + 63) / 64];
+
+  const int lc = threadIdx.x / CT;
+  const int t = threadIdx.x - lc * CT;
+  double* lam = lds + lc * (K::CORR_CELL_BYTES / 8);   // [2D][NF]
+  double* Fs = lam + 2 * D * NF;                        // [2D][NF][M]
+  double* sm = Fs + 2 * D * NF * M;                     // [2D]
+  const double cdt = (*p.dt) * p.inv_h;
+  const int64_t groups = (p.ncells + K::CCPB - 1) / K::CCPB;
+  double lmax = 0.0;
+  int bad = 0;
+
+  for (GroupIter it(groups); it.g < it.end; it.g += it.step) {
+    const int64_t cell = it.g * K::CCPB + lc;
+    const bool live = cell < p.ncells;
+    // -- solveRiemann on the 2d faces: one thread per (face, face node) --
+    double fh[M], dq[M];
+    const bool ftask = live && t < K::FT;
+    if (ftask) {
+      const int f = t / NF, b = t - f * NF;
+      const int i = f >> 1, s = f & 1;
+      const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
+      const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
+      const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b * M;
+      const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b * M;
+      double qL[M], qR[M], fL[M], fR[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        qL[v] = (double)trL[v];
+        qR[v] = (double)trR[v];
+      }
+      const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
+      const auto pR = PDE::template cell<double>(p.par + cR * K::NPAR);
+      double l = 0.0;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        if (i == I) {
+          if constexpr (K::NQ == 2) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+              fL[v] = (double)trL[NF * M + v];
+              fR[v] = (double)trR[NF * M + v];
+            }
+          } else {
+            PDE::template flux<I>(qL, fL, p.g, pL);
+            PDE::template flux<I>(qR, fR, p.g, pR);
+          }
+          l = fmax(PDE::template speed<I>(qL, p.g, pL), PDE::template speed<I>(qR, p.g, pR));
+        }
+      });
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        fh[v] = 0.5 * (fL[v] + fR[v]);
+        dq[v] = qR[v] - qL[v];
+      }
+      lam[f * NF + b] = l;
+    }
+    __syncthreads();
+    if (live && t < 2 * D) {
+      double s = 0.0;
+      for (int b = 0; b < NF; ++b) s = fmax(s, lam[t * NF + b]);
+      sm[t] = s;
+    }
+    __syncthreads();
+    if (ftask) {
+      const int f = t / NF, b = t - f * NF;
+      const double hs = 0.5 * sm[f];
+#pragma unroll
+      for (int v = 0; v < M; ++v) Fs[(f * NF + b) * M + v] = fh[v] - hs * dq[v];
+    }
+    __syncthreads();
+    // -- integrateFace + update + calcTimeStep: one thread per node --
+    if (live && t < NS) {
+      const int a = t;
+      double Qn[M];
+      double* Qp = p.Q + (cell * NS + a) * M;
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        const int k = coord<n, I>(a);
+        const int b = face_node<n, I>(a);
+        const double* Fm = Fs + ((2 * I) * NF + b) * M;
+        const double* Fp = Fs + ((2 * I + 1) * NF + b) * M;
+        const double lr = p.LR[k], ll = p.LL[k];
+#pragma unroll
+        for (int v = 0; v < M; ++v) Qn[v] -= cdt * (lr * Fp[v] - ll * Fm[v]);
+      });
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qp[v] = Qn[v];
+      const auto pc = PDE::template cell<double>(p.par + cell * K::NPAR);
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        lmax = fmax(lmax, PDE::template speed<I>(Qn, p.g, pc));
+      });
+      if (!PDE::admissible(Qn, p.g, pc)) {
+        bool fin = true;
+#pragma unroll
+        for (int v = 0; v < M; ++v) fin = fin && isfinite(Qn[v]);
+        bad |= fin ? 2 : 1;
+      }
+    }
+    __syncthreads();
+  }
+  const double bm = block_max<K::CTHREADS>(lmax, red);
+  if (threadIdx.x == 0) p.partial[blockIdx.x] = bm;
+  if (bad && p.flag) atomicOr(p.flag, bad);
+}
+
+template <class K>
+struct LamP {
+  const double* Q;
+  const double* par;
+  double* partial;
+  int64_t ncells;
+  Gconst<double> g;
+};
+
+template <class K>
+__global__ void __launch_bounds__(256) k_lam(const LamP<K> p) {
+  using PDE = typename K::PDE;
+  constexpr int M = K::M, NS = K::NS, D = K::D;
+  __shared__ double red[4];
+  const int64_t total = p.ncells * NS;
+  double lmax = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256) {
+    const int64_t cell = k / NS;
+    double q[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) q[v] = p.Q[k * M + v];
+    const auto pc = PDE::template cell<double>(p.par + cell * K::NPAR);
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      lmax = fmax(lmax, PDE::template speed<I>(q, p.g, pc));
+    });
+  }
+  const double bm = block_max<256>(lmax, red);
+  if (threadIdx.x == 0) p.partial[blockIdx.x] = bm;
+}
+
+// ---------------------------------------------------------------------------
+template <class K>
+int launch_predict(const LaunchArgs& a) {
+  using Real = typename K::Real;
+  PredP<K> p;
+  p.Q = a.Q;
+  p.par = a.params;
+  p.dt = a.dt;
+  p.tr = reinterpret_cast<Real*>(a.traces);
+  p.ncells = a.ncells;
+  p.inv_h = a.inv_h;
+  p.R = a.R;
+  for (int k = 0; k < 4; ++k) p.g.c[k] = (Real)a.gp[k];
+  p.t = make_ktab<K::n, Real>(*a.tab);
+  const int64_t blocks = (a.ncells + K::CPB - 1) / K::CPB;
+  hipLaunchKernelGGL(k_pred<K>, dim3((unsigned)blocks), dim3(K::THREADS), 0, a.stream, p);
+  return (int)hipGetLastError();
+}
+
+template <class K>
+int64_t reduce_grid(int64_t groups) {
+  if (groups < 64) return groups;
+  int64_t G = groups < kMaxReduceBlocks ? groups : kMaxReduceBlocks;
+  return G - G % 8;
+}
+
+template <class K>
+int launch_correct(const LaunchArgs& a) {
+  CorrP<K> p;
+  p.Q = a.Q;
+  p.par = a.params;
+  p.dt = a.dt;
+  p.tr = reinterpret_cast<const typename K::Real*>(a.traces);
+  p.partial = a.partial;
+  p.flag = a.flag;
+  p.ncells = a.ncells;
+  for (int k = 0; k < 3; ++k) p.nc[k] = a.nc[k];
+  p.inv_h = a.inv_h;
+  for (int k = 0; k < 4; ++k) p.g.c[k] = a.gp[k];
+  for (int k = 0; k < K::n; ++k) {
+    p.LL[k] = a.tab->LL[k];
+    p.LR[k] = a.tab->LR[k];
+  }
+  const int64_t groups = (a.ncells + K::CCPB - 1) / K::CCPB;
+  const int64_t G = reduce_grid<K>(groups);
+  if (G > a.n_partial) return (int)hipErrorInvalidValue;
+  *a.n_partial_used = G;
+  hipLaunchKernelGGL(k_corr<K>, dim3((unsigned)G), dim3(K::CTHREADS), 0, a.stream, p);
+  return (int)hipGetLastError();
+}
+
+template <class K>
+int launch_wave_speed(const LaunchArgs& a) {
+  LamP<K> p;
+  p.Q = a.Qc;
+  p.par = a.params;
+  p.partial = a.partial;
+  p.ncells = a.ncells;
+  for (int k = 0; k < 4; ++k) p.g.c[k] = a.gp[k];
+  int64_t G = (a.ncells * K::NS + 255) / 256;
+  if (G > 4096) G = 4096;
+  if (G > a.n_partial) return (int)hipErrorInvalidValue;
+  *a.n_partial_used = G;
+  hipLaunchKernelGGL(k_lam<K>, dim3((unsigned)G), dim3(256), 0, a.stream, p);
+  return (int)hipGetLastError();
+}
+
+template <class K>
+Launchers make_fwd_launchers() {
+  Launchers L;
+  L.predict = &launch_predict<K>;
+  L.correct = &launch_correct<K>;
+  L.wave_speed = &launch_wave_speed<K>;
+  L.trace_bytes_per_cell = K::TRACE_ELEMS * (int64_t)sizeof(typename K::Real);
+  return L;
+}
+
+}  // namespace adg

@@ -1,0 +1,167 @@
+// Device-side fluxes F_I(Q) and directional wave speeds for the four PDEs.
+//
+// Eq. (1) of the paper without non-conservative products, sources and point
+// sources (Sec. 3 neglects them):  dQ/dt + sum_i d/dx_i F_i(Q) = 0.
+// Euler is the paper's benchmark PDE (Sec. 7): Q = (rho, j, E),
+// F_i = (j_i, j_i j / rho + p e_i, j_i (E + p) / rho),
+// p = (gamma - 1)(E - |j|^2 / (2 rho)).
+//
+// Conventions shared by every PDE struct:
+//   M, NPAR, LINEAR        number of variables, per-cell parameters, linearity
+//   G<T>                   global constants in the working precision
+//   CP<T>                  per-cell constants derived from the cell parameters
+//   flux<I>(q, F, g, cp)   F = F_I(q), all M components
+//   speed<I>(q, g, cp)     largest |eigenvalue| of dF_I/dQ at q
+//   admissible(q, g, cp)   physical-state test used for the error flag
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace adg {
+
+template <class T> struct Gconst { T c[4]; };
+
+template <int D>
+struct Advection {
+  static constexpr int M = 1, NPAR = 0;
+  static constexpr bool LINEAR = true;
+  template <class T> struct CP { };
+  template <class T> __device__ static inline CP<T> cell(const double*) { return {}; }
+  template <int I, class T>
+  __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>&) {
+    F[0] = g.c[I] * q[0];
+  }
+  template <int I, class T>
+  __device__ static inline T speed(const T*, const Gconst<T>& g, const CP<T>&) {
+    return fabs(g.c[I]);
+  }
+  template <class T>
+  __device__ static inline bool admissible(const T* q, const Gconst<T>&, const CP<T>&) {
+    return isfinite(q[0]);
+  }
+};
+
+// g.c[0] = gamma, g.c[1] = gamma - 1
+template <int D>
+struct Euler {
+  static constexpr int M = D + 2, NPAR = 0;
+  static constexpr bool LINEAR = false;
+  template <class T> struct CP { };
+  template <class T> __device__ static inline CP<T> cell(const double*) { return {}; }
+  template <class T>
+  __device__ static inline T pressure(const T* q, T ir, const Gconst<T>& g) {
+    T jj = q[1] * q[1];
+#pragma unroll
+    for (int k = 1; k < D; ++k) jj += q[1 + k] * q[1 + k];
+    return g.c[1] * (q[D + 1] - T(0.5) * jj * ir);
+  }
+  template <int I, class T>
+  __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>&) {
+    const T ir = T(1) / q[0];
+    const T p = pressure(q, ir, g);
+    const T ui = q[1 + I] * ir;
+    F[0] = q[1 + I];
+#pragma unroll
+    for (int k = 0; k < D; ++k) F[1 + k] = q[1 + k] * ui;
+    F[1 + I] += p;
+    F[D + 1] = ui * (q[D + 1] + p);
+  }
+  template <int I, class T>
+  __device__ static inline T speed(const T* q, const Gconst<T>& g, const CP<T>&) {
+    const T ir = T(1) / q[0];
+    const T p = pressure(q, ir, g);
+    return fabs(q[1 + I] * ir) + sqrt(g.c[0] * p * ir);
+  }
+  template <class T>
+  __device__ static inline bool admissible(const T* q, const Gconst<T>& g, const CP<T>&) {
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < M; ++v) ok = ok && isfinite(q[v]);
+    if (!ok) return false;
+    const T ir = T(1) / q[0];
+    return q[0] > T(0) && pressure(q, ir, g) > T(0);
+  }
+};
+
+// Per cell: par[0] = sound speed c (rho_0 = 1, bulk modulus c^2).
+// Q = (p, u_1..u_D), F_i = (c^2 u_i, p e_i).
+template <int D>
+struct Acoustic {
+  static constexpr int M = D + 1, NPAR = 1;
+  static constexpr bool LINEAR = true;
+  template <class T> struct CP { T c, K; };
+  template <class T> __device__ static inline CP<T> cell(const double* par) {
+    const double c = par[0];
+    return {T(c), T(c * c)};
+  }
+  template <int I, class T>
+  __device__ static inline void flux(const T* q, T* F, const Gconst<T>&, const CP<T>& cp) {
+    F[0] = cp.K * q[1 + I];
+#pragma unroll
+    for (int k = 0; k < D; ++k) F[1 + k] = (k == I) ? q[0] : T(0);
+  }
+  template <int I, class T>
+  __device__ static inline T speed(const T*, const Gconst<T>&, const CP<T>& cp) { return cp.c; }
+  template <class T>
+  __device__ static inline bool admissible(const T* q, const Gconst<T>&, const CP<T>&) {
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < M; ++v) ok = ok && isfinite(q[v]);
+    return ok;
+  }
+};
+
+// Per cell: par = (rho, lambda, mu).  Velocity-stress form, stresses in
+// Voigt order (11,22,33,12,23,13) in 3D and (11,22,12) in 2D.
+// F_i(v_k) = -sigma_ik / rho,
+// F_i(sigma_kl) = -(lambda delta_kl v_i + mu (delta_ik v_l + delta_il v_k)).
+template <int D>
+struct Elastic {
+  static constexpr int NS_ = (D == 3) ? 6 : 3;
+  static constexpr int M = D + NS_, NPAR = 3;
+  static constexpr bool LINEAR = true;
+  template <class T> struct CP { T irho, lam, mu, cp; };
+  template <class T> __device__ static inline CP<T> cell(const double* par) {
+    const double rho = par[0], lam = par[1], mu = par[2];
+    return {T(1.0 / rho), T(lam), T(mu), T(sqrt((lam + 2.0 * mu) / rho))};
+  }
+  // Voigt slot of the symmetric pair (k, l)
+  __host__ __device__ static constexpr int slot(int k, int l) {
+    return (D == 3)
+               ? ((k == l) ? k : ((k + l == 1) ? 3 : ((k + l == 3) ? 4 : 5)))
+               : ((k == l) ? k : 2);
+  }
+  __host__ __device__ static constexpr int vk(int s) {   // first index of slot s
+    return (D == 3) ? (s < 3 ? s : (s == 3 ? 0 : (s == 4 ? 1 : 0)))
+                    : (s < 2 ? s : 0);
+  }
+  __host__ __device__ static constexpr int vl(int s) {   // second index of slot s
+    return (D == 3) ? (s < 3 ? s : (s == 3 ? 1 : (s == 4 ? 2 : 2)))
+                    : (s < 2 ? s : 1);
+  }
+  template <int I, class T>
+  __device__ static inline void flux(const T* q, T* F, const Gconst<T>&, const CP<T>& cp) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) F[k] = -q[D + slot(I, k)] * cp.irho;
+#pragma unroll
+    for (int s = 0; s < NS_; ++s) {
+      const int k = vk(s), l = vl(s);
+      T t = T(0);
+      if (I == k) t += cp.mu * q[l];
+      if (I == l) t += cp.mu * q[k];
+      if (k == l) t += cp.lam * q[I];
+      F[D + s] = -t;
+    }
+  }
+  template <int I, class T>
+  __device__ static inline T speed(const T*, const Gconst<T>&, const CP<T>& cp) { return cp.cp; }
+  template <class T>
+  __device__ static inline bool admissible(const T* q, const Gconst<T>&, const CP<T>&) {
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < M; ++v) ok = ok && isfinite(q[v]);
+    return ok;
+  }
+};
+
+}  // namespace adg

@@ -1,0 +1,29 @@
+// Compile-time registry: which (dim, order, precision) combinations of a PDE
+// are instantiated.  Included by exactly one instantiation unit per PDE.
+#pragma once
+
+#include "kernels_fwd.hpp"
+
+namespace adg {
+
+template <template <int> class PDET, int D, int N>
+const Launchers* pick_precision(int prec) {
+  if (prec == 0) {
+    static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, double>>();
+    return &L;
+  }
+  if (prec == 1) {
+    static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, float>>();
+    return &L;
+  }
+  return nullptr;
+}
+
+template <template <int> class PDET, int D, int... Ns>
+const Launchers* pick_order(int order, int prec) {
+  const Launchers* r = nullptr;
+  ((order == Ns ? (r = pick_precision<PDET, D, Ns>(prec), 0) : 0), ...);
+  return r;
+}
+
+}  // namespace adg

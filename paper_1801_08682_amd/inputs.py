@@ -1,0 +1,196 @@
+"""Seeded synthetic inputs and the five named workloads.
+
+This module generates inputs only: grid geometry, initial states and per-cell
+materials.  It holds none of the method's arithmetic, so the GPU path and the
+CPU oracle (which never imports it) can be fed the same arrays.  Node
+positions of the Gauss-Legendre points come from numpy's library routine.
+
+Random numbers: ``numpy.random.default_rng(seed)`` (PCG64), float64, on the
+host.  Seeds: materials / sound speed / Fourier field 0, receivers 1, the
+"true" sound speed of the misfit data 2, finite-difference directions 3.
+"""
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+ADVECTION, EULER, ELASTIC, ACOUSTIC = 0, 1, 2, 3
+FP64, FP32, BF16 = 0, 1, 2
+
+
+def n_vars(pde, dim):
+    if pde == ADVECTION:
+        return 1
+    if pde == EULER:
+        return dim + 2
+    if pde == ACOUSTIC:
+        return dim + 1
+    return dim + (6 if dim == 3 else 3)
+
+
+def n_params(pde):
+    return {ADVECTION: 0, EULER: 0, ACOUSTIC: 1, ELASTIC: 3}[pde]
+
+
+@dataclass
+class Workload:
+    """One synthetic run: grid, PDE, order and stepping."""
+    name: str
+    pde: int
+    dim: int
+    order: int
+    n_cells: tuple
+    length: float = 1.0
+    pde_param: tuple = ()
+    picard_iters: int = 0
+    precision: int = FP64
+    cfl: float = 0.9
+    steps: int = 1
+    adaptive_dt: bool = False
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.order + 1
+
+    @property
+    def m(self):
+        return n_vars(self.pde, self.dim)
+
+    @property
+    def ncells(self):
+        return int(np.prod(self.n_cells))
+
+    @property
+    def h(self):
+        return self.length / self.n_cells[0]
+
+    @property
+    def dofs_per_cell(self):
+        return self.m * self.n ** self.dim
+
+    @property
+    def npar(self):
+        return n_params(self.pde)
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+def preset(name):
+    """The five workloads of the benchmark plan (C1..C5)."""
+    if name == "C1":   # 2D advection, exact solution known
+        return Workload("C1", ADVECTION, 2, 3, (27, 27), 1.0, (1.0, 0.5),
+                        steps=10, extra={"ic": "sine"})
+    if name == "C2":   # 3D Euler N=4 on 81^3: the headline workload
+        return Workload("C2", EULER, 3, 4, (81, 81, 81), 1.0, (1.4,),
+                        steps=100, adaptive_dt=True, extra={"ic": "bump"})
+    if name == "C3":   # 3D elasticity N=5, 64^3, random materials
+        return Workload("C3", ELASTIC, 3, 5, (64, 64, 64), 1.0, (),
+                        steps=200, extra={"ic": "pulse"})
+    if name == "C4":   # 3D acoustics N=3, 48^3, receivers and adjoint
+        return Workload("C4", ACOUSTIC, 3, 3, (48, 48, 48), 1.0, (),
+                        steps=200, extra={"ic": "pressure", "checkpoint": 20})
+    if name == "C5":   # 3D Euler N=7, 48^3, Fourier density
+        return Workload("C5", EULER, 3, 7, (48, 48, 48), 1.0, (1.4,),
+                        steps=50, adaptive_dt=True,
+                        extra={"ic": "fourier", "checkpoint": 10})
+    raise KeyError(name)
+
+
+def gl_nodes_unit(n):
+    """Gauss-Legendre nodes on [0, 1] (numpy library routine)."""
+    z, _ = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (1.0 + z)
+
+
+def node_positions(wl):
+    """Physical coordinates of every nodal point: (ncells, n^dim, dim).
+
+    Cells lexicographic with x fastest; nodes lexicographic with k_x fastest.
+    """
+    d, n = wl.dim, wl.n
+    xi = gl_nodes_unit(n)
+    h = wl.h
+    axes_c = [np.arange(wl.n_cells[i]) for i in range(d)]
+    # cell multi-index with x fastest
+    cidx = np.stack(np.meshgrid(*reversed(axes_c), indexing="ij"), -1)
+    cidx = cidx.reshape(-1, d)[:, ::-1]                     # (C, d): (ix, iy, iz)
+    nidx = np.stack(np.meshgrid(*([np.arange(n)] * d), indexing="ij"), -1)
+    nidx = nidx.reshape(-1, d)[:, ::-1]                     # (n^d, d): (kx, ky, kz)
+    X = (cidx[:, None, :] + xi[nidx][None, :, :]) * h
+    return X
+
+
+def _periodic_r2(X, centre, L):
+    dx = X - centre
+    dx = dx - L * np.round(dx / L)
+    return (dx * dx).sum(-1)
+
+
+def initial_state(wl, seed=0):
+    """Q0[cell][node][var] (float64) of the workload's initial condition."""
+    X = node_positions(wl)
+    d, m, L = wl.dim, wl.m, wl.length
+    ic = wl.extra.get("ic", "sine")
+    Q = np.zeros(X.shape[:2] + (m,))
+    if ic == "sine":
+        Q[..., 0] = np.sin(2 * np.pi * X.sum(-1))
+    elif ic == "bump":                       # Euler: rho bump, u = 0, p = 1
+        g = wl.pde_param[0] if wl.pde_param else 1.4
+        r2 = _periodic_r2(X, 0.5 * L, L)
+        Q[..., 0] = 1.0 + 0.1 * np.exp(-r2 / (2 * 0.1 ** 2))
+        Q[..., d + 1] = 1.0 / (g - 1.0)
+    elif ic == "fourier":                    # Euler: rho Fourier modes, p = rho^gamma
+        g = wl.pde_param[0] if wl.pde_param else 1.4
+        rng = np.random.default_rng(seed)
+        rho = np.ones(X.shape[:2])
+        for _ in range(8):
+            k = rng.integers(-4, 5, size=d)
+            while not k.any():
+                k = rng.integers(-4, 5, size=d)
+            a = rng.uniform(-1.0, 1.0)
+            ph = rng.uniform(0.0, 2 * np.pi)
+            rho += 0.05 * a * np.cos(2 * np.pi * (X @ k) / L + ph)
+        Q[..., 0] = rho
+        Q[..., d + 1] = rho ** g / (g - 1.0)
+    elif ic == "pulse":                      # elasticity: v_1 pulse
+        Q[..., 0] = np.exp(-_periodic_r2(X, 0.5 * L, L) / (2 * 0.1 ** 2))
+    elif ic == "pressure":                   # acoustics: p pulse
+        Q[..., 0] = np.exp(-_periodic_r2(X, 0.5 * L, L) / (2 * 0.1 ** 2))
+    else:
+        raise KeyError(ic)
+    return Q
+
+
+def cell_params(wl, seed=0):
+    """Per-cell material parameters (ncells, npar) or None."""
+    rng = np.random.default_rng(seed)
+    C = wl.ncells
+    if wl.pde == ACOUSTIC:
+        return rng.uniform(0.9, 1.1, size=(C, 1))
+    if wl.pde == ELASTIC:
+        return rng.uniform(0.8, 1.2, size=(C, 3)) * np.array([1.0, 2.0, 1.0])
+    return None
+
+
+def random_state(wl, seed, amplitude=0.1):
+    """A seeded, physically admissible random state for parity tests.
+
+    Euler: rho = 1 + amp*U(-1,1), j = amp*U(-1,1), E such that p = 1 + amp*U(-1,1).
+    Linear PDEs: U(-1, 1) per DoF.
+    """
+    rng = np.random.default_rng(seed)
+    C, nn, m, d = wl.ncells, wl.n ** wl.dim, wl.m, wl.dim
+    if wl.pde == EULER:
+        g = wl.pde_param[0] if wl.pde_param else 1.4
+        rho = 1.0 + amplitude * rng.uniform(-1, 1, size=(C, nn))
+        j = amplitude * rng.uniform(-1, 1, size=(C, nn, d))
+        p = 1.0 + amplitude * rng.uniform(-1, 1, size=(C, nn))
+        E = p / (g - 1.0) + 0.5 * (j * j).sum(-1) / rho
+        return np.concatenate([rho[..., None], j, E[..., None]], -1)
+    return rng.uniform(-1.0, 1.0, size=(C, nn, m))
+
+
+def receivers(n, dim, seed=1, length=1.0):
+    return np.random.default_rng(seed).uniform(0.0, length, size=(n, dim))

@@ -1,0 +1,106 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs, element-wise (per-field relative L2, absolute where a
+field's reference norm is negligible).  FP64 bar: 1e-12."""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1801_08682_amd import inputs
+from tests.helpers import gpu_run, max_rel, oracle_run, per_field, setup_of
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def _wl(pde, dim, order, n_cells, pp=(), prec=inputs.FP64, R=0):
+    h = 1.0 / 9.0
+    return inputs.Workload(f"t{pde}{dim}{order}", pde, dim, order, tuple(n_cells),
+                           n_cells[0] * h, tuple(pp), picard_iters=R, precision=prec)
+
+
+def test_c1_full_parity_and_exact():
+    """C1 at full size: 27x27 advection N=3, 10 steps, fixed dt."""
+    wl = inputs.preset("C1")
+    Q0 = inputs.initial_state(wl)
+    dt = wl.cfl * wl.h / (wl.dim * (2 * wl.order + 1) * 1.0)
+    print("case C1 dt", dt, flush=True)
+    Qg, flag, _ = gpu_run(wl, Q0, None, wl.steps, dt=dt)
+    Qo, _ = oracle_run(wl, Q0, None, wl.steps, dt=dt)
+    assert flag == 0
+    err = max_rel(Qg, Qo, wl)
+    print("C1 rel L2 vs oracle", err)
+    assert err < TOL64
+    X = inputs.node_positions(wl)
+    ex = np.sin(2 * np.pi * (X.sum(-1) - 1.5 * wl.steps * dt))[..., None]
+    assert max_rel(Qg, torch.tensor(ex), wl) < 2e-6
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4, 5])
+def test_euler_2d_orders(order):
+    wl = _wl(inputs.EULER, 2, order, (5, 3), (1.4,))
+    Q0 = inputs.random_state(wl, seed=10 + order, amplitude=0.05)
+    print("case euler2d N", order, flush=True)
+    Qg, flag, dg = gpu_run(wl, Q0, None, 3, cfl=0.5, record_dt=True)
+    Qo, do = oracle_run(wl, Q0, None, 3, cfl=0.5)
+    assert flag == 0
+    assert np.allclose(dg, do, rtol=1e-13, atol=0)
+    assert max_rel(Qg, Qo, wl) < TOL64, per_field(Qg, Qo, wl)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 5, 7])
+def test_euler_3d_orders(order):
+    """Ragged grid (cells not a multiple of any block size)."""
+    wl = _wl(inputs.EULER, 3, order, (3, 2, 2) if order >= 5 else (5, 3, 2), (1.4,))
+    Q0 = inputs.random_state(wl, seed=20 + order, amplitude=0.05)
+    print("case euler3d N", order, flush=True)
+    Qg, flag, dg = gpu_run(wl, Q0, None, 2, cfl=0.5, record_dt=True)
+    Qo, do = oracle_run(wl, Q0, None, 2, cfl=0.5)
+    assert flag == 0
+    assert np.allclose(dg, do, rtol=1e-13, atol=0)
+    assert max_rel(Qg, Qo, wl) < TOL64, per_field(Qg, Qo, wl)
+
+
+@pytest.mark.parametrize("dim,order", [(2, 2), (3, 1), (3, 3), (3, 5)])
+def test_acoustic(dim, order):
+    wl = _wl(inputs.ACOUSTIC, dim, order, (4, 3, 2)[:dim])
+    Q0 = inputs.random_state(wl, seed=30 + order)
+    par = inputs.cell_params(wl, seed=0)
+    print("case acoustic", dim, order, flush=True)
+    Qg, flag, _ = gpu_run(wl, Q0, par, 2, dt=1e-3)
+    Qo, _ = oracle_run(wl, Q0, par, 2, dt=1e-3)
+    assert max_rel(Qg, Qo, wl) < TOL64, per_field(Qg, Qo, wl)
+
+
+@pytest.mark.parametrize("dim,order", [(2, 3), (3, 2), (3, 5)])
+def test_elastic(dim, order):
+    wl = _wl(inputs.ELASTIC, dim, order, (3, 2, 2)[:dim])
+    Q0 = inputs.random_state(wl, seed=40 + order)
+    par = inputs.cell_params(wl, seed=0)
+    print("case elastic", dim, order, flush=True)
+    Qg, flag, _ = gpu_run(wl, Q0, par, 2, dt=1e-3)
+    Qo, _ = oracle_run(wl, Q0, par, 2, dt=1e-3)
+    assert max_rel(Qg, Qo, wl) < TOL64, per_field(Qg, Qo, wl)
+
+
+@pytest.mark.parametrize("dim,order", [(2, 0), (3, 4)])
+def test_advection(dim, order):
+    wl = _wl(inputs.ADVECTION, dim, order, (4, 3, 2)[:dim], (1.0, -0.5, 0.25)[:dim])
+    Q0 = inputs.random_state(wl, seed=50 + order)
+    print("case advection", dim, order, flush=True)
+    Qg, flag, _ = gpu_run(wl, Q0, None, 3, dt=2e-3)
+    Qo, _ = oracle_run(wl, Q0, None, 3, dt=2e-3)
+    assert max_rel(Qg, Qo, wl) < TOL64, per_field(Qg, Qo, wl)
+
+
+def test_fp32_predictor_error_is_stated():
+    """Mixed precision (float predictor, float64 corrector) against the FP64
+    oracle: the error is small and far above FP64 round-off."""
+    wl = _wl(inputs.EULER, 3, 4, (4, 3, 3), (1.4,), prec=inputs.FP32)
+    Q0 = inputs.random_state(wl, seed=60)
+    print("case fp32 euler3d", flush=True)
+    Qg, flag, _ = gpu_run(wl, Q0, None, 2, dt=1e-3)
+    Qo, _ = oracle_run(wl, Q0, None, 2, dt=1e-3)
+    pf = per_field(Qg, Qo, wl)
+    print("fp32 per-field rel L2", pf)
+    assert max(pf) < 1e-5
