@@ -104,3 +104,57 @@ def test_fp32_predictor_error_is_stated():
     pf = per_field(Qg, Qo, wl)
     print("fp32 per-field rel L2", pf)
     assert max(pf) < 1e-5
+
+
+def test_c2_full_size_sampled_parity():
+    """C2 at full size (81^3, N=4) in the bench's launch configuration: one
+    step on the GPU; 24 sampled cells (corners, edges, bump centre, random)
+    recomputed by the oracle cell by cell; plus conservation over the grid."""
+    from oracle import step as ostep
+    from oracle.diagnostics import totals
+    wl = inputs.preset("C2")
+    Q0 = inputs.initial_state(wl)
+    s = setup_of(wl)
+    lam = ostep.max_wave_speed(torch.tensor(Q0[::97]), None, s)
+    print("case C2 full one step", flush=True)
+    from paper_1801_08682_amd.stepper import Stepper
+    st = Stepper(wl)
+    Q = torch.tensor(Q0, device="cuda")
+    lamd = st.scalar()
+    dtd = st.scalar()
+    st.wave_speed(Q, None)
+    st.cfl_dt(wl.cfl, lamd, dtd)
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st.step(Q, None, dtd, flag)
+    torch.cuda.synchronize()
+    dt = float(dtd.item())
+    assert abs(float(lamd.item()) - ostep.max_wave_speed(torch.tensor(Q0), None, s)) < 1e-14
+    assert int(flag.item()) == 0
+    rng = np.random.default_rng(0)
+    nc = 81
+    c = lambda x, y, z: x + nc * (y + nc * z)
+    cells = [c(0, 0, 0), c(80, 80, 80), c(40, 40, 40), c(0, 40, 80), c(80, 0, 40),
+             c(39, 40, 41), c(40, 41, 40)] + list(rng.integers(0, nc ** 3, 17))
+    ref = ostep.step_cells(torch.tensor(Q0), None, dt, s, cells)
+    got = Q[torch.tensor(cells, device="cuda")].cpu()
+    err = (got - ref).abs().max() / ref.abs().max()
+    print("C2 sampled max rel err", float(err))
+    assert float(err) < 1e-13
+    M0 = totals(torch.tensor(Q0), s)
+    M1 = totals(Q.cpu(), s)
+    assert float((M1 - M0).abs().max()) < 1e-13 * float(M0.abs().max())
+    st.close()
+
+
+def test_bitwise_determinism_and_flag():
+    """Run-to-run bitwise determinism (no float atomics), and the
+    admissibility flag for a negative density."""
+    wl = _wl(inputs.EULER, 3, 3, (6, 5, 4), (1.4,))
+    Q0 = inputs.random_state(wl, seed=70, amplitude=0.05)
+    a, fa, _ = gpu_run(wl, Q0, None, 3, dt=1e-3)
+    b, fb, _ = gpu_run(wl, Q0, None, 3, dt=1e-3)
+    assert torch.equal(a, b) and fa == 0 and fb == 0
+    Qbad = Q0.copy()
+    Qbad[7, :, 0] = -0.5
+    _, fbad, _ = gpu_run(wl, Qbad, None, 1, dt=1e-4)
+    assert fbad & 2
