@@ -48,6 +48,7 @@ template <int n, class Real>
 struct KTab {
   Real D[n][n];     // derivative matrix (Picard contractions)
   Real P[n][n];     // Picard time operator
+  Real Ps[n];       // row sums of P (time operator applied to a constant)
   double w[n];      // GL weights (time averages)
   double Kv[n][n];  // volume operator
   double FL[n], FR[n], LL[n], LR[n];
@@ -57,6 +58,7 @@ template <int n, class Real>
 inline KTab<n, Real> make_ktab(const HostTables& h) {
   KTab<n, Real> t;
   for (int a = 0; a < n; ++a) {
+    double ps = 0.0;
     t.w[a] = h.w[a];
     t.FL[a] = h.FL[a];
     t.FR[a] = h.FR[a];
@@ -65,8 +67,10 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
     for (int j = 0; j < n; ++j) {
       t.D[a][j] = (Real)h.D[a * n + j];
       t.P[a][j] = (Real)h.P[a * n + j];
+      ps += h.P[a * n + j];
       t.Kv[a][j] = h.Kv[a * n + j];
     }
+    t.Ps[a] = (Real)ps;
   }
   return t;
 }

@@ -21,7 +21,13 @@
 
 #include "common.hpp"
 
+#ifndef ADG_PLANE_PAD
+#define ADG_PLANE_PAD 0
+#endif
+
 namespace adg {
+
+constexpr int PLANE_PAD = ADG_PLANE_PAD;
 
 template <int D_, int N_, template <int> class PDET, class Real_>
 struct Fwd {
@@ -34,8 +40,11 @@ struct Fwd {
   // predictor block
   static constexpr int CPB = (NS >= 128) ? 1 : 128 / NS;
   static constexpr int THREADS = CPB * NS;
+  // LDS plane stride (one time slice, one variable): NS plus padding that
+  // shifts consecutive planes across the LDS banks
+  static constexpr int NSP = NS + PLANE_PAD;
   static constexpr int LDS_BUDGET = 80 * 1024;
-  static constexpr int SLICE_BYTES = 2 * NS * M * (int)sizeof(Real);
+  static constexpr int SLICE_BYTES = 2 * NSP * M * (int)sizeof(Real);
   static constexpr int pick_S() {
     for (int s = n; s > 1; --s)
       if (CPB * s * SLICE_BYTES <= LDS_BUDGET) return s;
@@ -43,9 +52,9 @@ struct Fwd {
   }
   static constexpr int S = pick_S();
   static constexpr int NB = (n + S - 1) / S;                 // batches per iteration
-  static constexpr int PIC_BYTES = 2 * S * NS * M * (int)sizeof(Real);
+  static constexpr int PIC_BYTES = 2 * S * NSP * M * (int)sizeof(Real);
   static constexpr int FIN_BYTES = 3 * NS * M * 8;
-  static constexpr int CELL_BYTES = PIC_BYTES > FIN_BYTES ? PIC_BYTES : FIN_BYTES;
+  static constexpr int CELL_BYTES = ((PIC_BYTES > FIN_BYTES ? PIC_BYTES : FIN_BYTES) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
   static constexpr int64_t TRACE_ELEMS = 2LL * D * NQ * NF * M;   // per cell
@@ -75,6 +84,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   using Real = typename K::Real;
   using PDE = typename K::PDE;
   constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, S = K::S, D = K::D;
+  constexpr int NSP = K::NSP;
   __shared__ __align__(16) unsigned char smem[K::LDS_BYTES];
 
   const int lc = threadIdx.x / NS;
@@ -83,8 +93,8 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   const bool live = cell < p.ncells;
   const int64_t cs = live ? cell : 0;
   unsigned char* base = smem + lc * K::CELL_BYTES;
-  Real* Qs = reinterpret_cast<Real*>(base);
-  Real* Rs = Qs + S * NS * M;
+  Real* Qs = reinterpret_cast<Real*>(base);      // [S][M][NSP]: q of S time slices
+  Real* Rs = Qs + S * NSP * M;                   // [S][M][NSP]: sum_i D_i F_i(q)
 
   const double cdt = (*p.dt) * p.inv_h;   // dt / h
   const Real c = (Real)cdt;
@@ -99,8 +109,72 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
 #pragma unroll
     for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v];
 
+  // Node role: publish time slices [t0, t0 + ns) of this node's column.
+  auto publish = [&](auto T0_, auto NS_) {
+    constexpr int t0 = decltype(T0_)::value, ns = decltype(NS_)::value;
+#pragma unroll
+    for (int tt = 0; tt < ns; ++tt)
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qs[(tt * M + v) * NSP + a] = q[t0 + tt][v];
+  };
+  // Pencil role: for every published slice and axis I, evaluate F_I along a
+  // pencil and contract with D; the three axis results are summed in Rs.
+  auto contract = [&](auto NS_) {
+    constexpr int ns = decltype(NS_)::value;
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      auto pencil = [&](int tt, int b) {
+        const Real* qsl = Qs + tt * M * NSP;
+        Real out[n][M];
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+#pragma unroll
+          for (int v = 0; v < M; ++v) out[k][v] = Real(0);
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const int nd = pencil_node<n, I>(b, j);
+          Real qn[M], F[M];
+#pragma unroll
+          for (int v = 0; v < M; ++v) qn[v] = qsl[v * NSP + nd];
+          PDE::template flux<I>(qn, F, p.g, cp);
+#pragma unroll
+          for (int k = 0; k < n; ++k)
+#pragma unroll
+            for (int v = 0; v < M; ++v) out[k][v] = fma(p.t.D[k][j], F[v], out[k][v]);
+        }
+        Real* rsl = Rs + tt * M * NSP;
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const int nd = pencil_node<n, I>(b, k);
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            if constexpr (I == 0) rsl[v * NSP + nd] = out[k][v];
+            else rsl[v * NSP + nd] += out[k][v];
+          }
+        }
+      };
+      if constexpr (ns * NF == NS) {
+        pencil(a / NF, a % NF);                  // exactly one task per thread
+      } else {
+        for (int task = a; task < ns * NF; task += NS) pencil(task / NF, task % NF);
+      }
+      __syncthreads();
+    });
+  };
+
   // ---- predict: Picard iteration q <- u - (dt/h) P sum_i D_i F_i(q) ----
-  for (int r = 0; r < p.R; ++r) {
+  // First iteration: q = u is constant in time, so sum_i D_i F_i(q) is the
+  // same on every slice and P reduces to its row sums (one slice computed).
+  publish(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+  __syncthreads();
+  contract(std::integral_constant<int, 1>{});
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const Real rv = Rs[v * NSP + a];
+#pragma unroll
+    for (int t = 0; t < n; ++t) q[t][v] = (Real)u[v] - c * (p.t.Ps[t] * rv);
+  }
+  for (int r = 1; r < p.R; ++r) {
     Real acc[n][M];
 #pragma unroll
     for (int t = 0; t < n; ++t)
@@ -110,58 +184,18 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
     static_for<0, K::NB>([&](auto B_) {
       constexpr int t0 = decltype(B_)::value * S;
       constexpr int ns = (n - t0) < S ? (n - t0) : S;
-#pragma unroll
-      for (int tt = 0; tt < ns; ++tt)
-#pragma unroll
-        for (int v = 0; v < M; ++v) Qs[(tt * M + v) * NS + a] = q[t0 + tt][v];
+      if constexpr (K::NB > 1) __syncthreads();   // Qs/Rs reuse across batches
+      publish(std::integral_constant<int, t0>{}, std::integral_constant<int, ns>{});
       __syncthreads();
-
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        for (int task = a; task < ns * NF; task += NS) {
-          const int tt = task / NF;
-          const int b = task - tt * NF;
-          const Real* qsl = Qs + tt * M * NS;
-          Real out[n][M];
-#pragma unroll
-          for (int k = 0; k < n; ++k)
-#pragma unroll
-            for (int v = 0; v < M; ++v) out[k][v] = Real(0);
-#pragma unroll
-          for (int j = 0; j < n; ++j) {
-            const int nd = pencil_node<n, I>(b, j);
-            Real qn[M], F[M];
-#pragma unroll
-            for (int v = 0; v < M; ++v) qn[v] = qsl[v * NS + nd];
-            PDE::template flux<I>(qn, F, p.g, cp);
-#pragma unroll
-            for (int k = 0; k < n; ++k)
-#pragma unroll
-              for (int v = 0; v < M; ++v) out[k][v] += p.t.D[k][j] * F[v];
-          }
-          Real* rsl = Rs + tt * M * NS;
-#pragma unroll
-          for (int k = 0; k < n; ++k) {
-            const int nd = pencil_node<n, I>(b, k);
-#pragma unroll
-            for (int v = 0; v < M; ++v) {
-              if constexpr (I == 0) rsl[v * NS + nd] = out[k][v];
-              else rsl[v * NS + nd] += out[k][v];
-            }
-          }
-        }
-        __syncthreads();
-      });
-
+      contract(std::integral_constant<int, ns>{});
 #pragma unroll
       for (int tt = 0; tt < ns; ++tt)
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          const Real rv = Rs[(tt * M + v) * NS + a];
+          const Real rv = Rs[(tt * M + v) * NSP + a];
 #pragma unroll
-          for (int t = 0; t < n; ++t) acc[t][v] += p.t.P[t][t0 + tt] * rv;
+          for (int t = 0; t < n; ++t) acc[t][v] = fma(p.t.P[t][t0 + tt], rv, acc[t][v]);
         }
-      __syncthreads();
     });
 
 #pragma unroll
@@ -169,6 +203,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
 #pragma unroll
       for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v] - c * acc[t][v];
   }
+  __syncthreads();   // LDS is reused below
 
   // ---- extrapolate + integrateVolume on time averages (float64) ----
   double* Fb = reinterpret_cast<double*>(base);

@@ -21,15 +21,36 @@ namespace adg {
 
 template <class T> struct Gconst { T c[4]; };
 
+// 1/x from the hardware reciprocal refined by Newton steps (double: two
+// steps, within a few ulp of the correctly rounded quotient).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// AUX > 0: the PDE caches one per-node value (aux) next to the state so that
+// the per-axis fluxes of a node can share it (Euler: 1/rho).
 template <int D>
 struct Advection {
-  static constexpr int M = 1, NPAR = 0;
+  static constexpr int M = 1, NPAR = 0, AUX = 0;
   static constexpr bool LINEAR = true;
   template <class T> struct CP { };
   template <class T> __device__ static inline CP<T> cell(const double*) { return {}; }
   template <int I, class T>
   __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>&) {
     F[0] = g.c[I] * q[0];
+  }
+  template <class T> __device__ static inline T aux(const T*) { return T(0); }
+  template <int I, class T>
+  __device__ static inline void flux_aux(const T* q, T, T* F, const Gconst<T>& g, const CP<T>& cp) {
+    flux<I>(q, F, g, cp);
   }
   template <int I, class T>
   __device__ static inline T speed(const T*, const Gconst<T>& g, const CP<T>&) {
@@ -44,7 +65,7 @@ struct Advection {
 // g.c[0] = gamma, g.c[1] = gamma - 1
 template <int D>
 struct Euler {
-  static constexpr int M = D + 2, NPAR = 0;
+  static constexpr int M = D + 2, NPAR = 0, AUX = 1;
   static constexpr bool LINEAR = false;
   template <class T> struct CP { };
   template <class T> __device__ static inline CP<T> cell(const double*) { return {}; }
@@ -55,9 +76,13 @@ struct Euler {
     for (int k = 1; k < D; ++k) jj += q[1 + k] * q[1 + k];
     return g.c[1] * (q[D + 1] - T(0.5) * jj * ir);
   }
+  template <class T> __device__ static inline T aux(const T* q) { return rcp(q[0]); }
   template <int I, class T>
-  __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>&) {
-    const T ir = T(1) / q[0];
+  __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>& cp) {
+    flux_aux<I>(q, rcp(q[0]), F, g, cp);
+  }
+  template <int I, class T>
+  __device__ static inline void flux_aux(const T* q, T ir, T* F, const Gconst<T>& g, const CP<T>&) {
     const T p = pressure(q, ir, g);
     const T ui = q[1 + I] * ir;
     F[0] = q[1 + I];
@@ -68,7 +93,7 @@ struct Euler {
   }
   template <int I, class T>
   __device__ static inline T speed(const T* q, const Gconst<T>& g, const CP<T>&) {
-    const T ir = T(1) / q[0];
+    const T ir = rcp(q[0]);
     const T p = pressure(q, ir, g);
     return fabs(q[1 + I] * ir) + sqrt(g.c[0] * p * ir);
   }
@@ -78,7 +103,7 @@ struct Euler {
 #pragma unroll
     for (int v = 0; v < M; ++v) ok = ok && isfinite(q[v]);
     if (!ok) return false;
-    const T ir = T(1) / q[0];
+    const T ir = rcp(q[0]);
     return q[0] > T(0) && pressure(q, ir, g) > T(0);
   }
 };
@@ -87,7 +112,7 @@ struct Euler {
 // Q = (p, u_1..u_D), F_i = (c^2 u_i, p e_i).
 template <int D>
 struct Acoustic {
-  static constexpr int M = D + 1, NPAR = 1;
+  static constexpr int M = D + 1, NPAR = 1, AUX = 0;
   static constexpr bool LINEAR = true;
   template <class T> struct CP { T c, K; };
   template <class T> __device__ static inline CP<T> cell(const double* par) {
@@ -99,6 +124,11 @@ struct Acoustic {
     F[0] = cp.K * q[1 + I];
 #pragma unroll
     for (int k = 0; k < D; ++k) F[1 + k] = (k == I) ? q[0] : T(0);
+  }
+  template <class T> __device__ static inline T aux(const T*) { return T(0); }
+  template <int I, class T>
+  __device__ static inline void flux_aux(const T* q, T, T* F, const Gconst<T>& g, const CP<T>& cp) {
+    flux<I>(q, F, g, cp);
   }
   template <int I, class T>
   __device__ static inline T speed(const T*, const Gconst<T>&, const CP<T>& cp) { return cp.c; }
@@ -118,7 +148,7 @@ struct Acoustic {
 template <int D>
 struct Elastic {
   static constexpr int NS_ = (D == 3) ? 6 : 3;
-  static constexpr int M = D + NS_, NPAR = 3;
+  static constexpr int M = D + NS_, NPAR = 3, AUX = 0;
   static constexpr bool LINEAR = true;
   template <class T> struct CP { T irho, lam, mu, cp; };
   template <class T> __device__ static inline CP<T> cell(const double* par) {
@@ -152,6 +182,11 @@ struct Elastic {
       if (k == l) t += cp.lam * q[I];
       F[D + s] = -t;
     }
+  }
+  template <class T> __device__ static inline T aux(const T*) { return T(0); }
+  template <int I, class T>
+  __device__ static inline void flux_aux(const T* q, T, T* F, const Gconst<T>& g, const CP<T>& cp) {
+    flux<I>(q, F, g, cp);
   }
   template <int I, class T>
   __device__ static inline T speed(const T*, const Gconst<T>&, const CP<T>& cp) { return cp.cp; }
