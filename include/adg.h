@@ -73,6 +73,7 @@ typedef struct {
   double pde_param[4];    /* see adg_pde */
   int32_t picard_iters;   /* R; 0 selects N + 1 */
   int32_t precision;      /* adg_precision */
+  int32_t adjoint;        /* nonzero: reserve workspace for adg_step_adjoint (FP64 only) */
 } adg_config;
 
 typedef struct adg_ctx adg_ctx;
@@ -83,7 +84,9 @@ typedef struct adg_ctx adg_ctx;
  *   workspace_bytes = device workspace the caller must pass to adg_init: the
  *                     time-integrated face hull (Theorem 1; Table 1 task
  *                     extrapolate, reduced to one time value per face node)
- *                     plus reduction scratch.
+ *                     plus reduction scratch; with cfg->adjoint also a copy
+ *                     of Q, the hull's bars and per-block Picard scratch
+ *                     (at most 1024 blocks, at most 2 GiB).
  * Any output pointer may be NULL.  Returns INVALID_ARG / UNSUPPORTED as above. */
 adg_status adg_query(const adg_config* cfg, int64_t* dofs_per_cell, int64_t* params_per_cell,
                      int64_t* workspace_bytes);
@@ -129,10 +132,14 @@ adg_status adg_wave_speed(adg_ctx* ctx, const double* d_Q, const double* d_param
 adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_dt);
 
 /* Reverse mode of one adg_step with dt held fixed (the discrete adjoint of
- * Eq. (5)/(6) including the Picard iterations and the Rusanov maximum):
+ * Eq. (5)/(6) including the Picard iterations and the Rusanov maximum; the
+ * maximum passes its derivative to the first maximal face node, left state
+ * before right):
  *   d_Qbar (in)  dJ/dQ(T + dt), (out) dJ/dQ(T), in place;
- *   d_params_bar (nullable) += dJ/dparams.
- * d_Qn is Q(T) and is not modified.  Uses the workspace. */
+ *   d_params_bar (nullable) += dJ/dparams, same layout as params.
+ * d_Qn is Q(T) and is not modified.  Needs a context created with
+ * cfg->adjoint != 0 and precision ADG_FP64 (else ADG_ERR_WORKSPACE /
+ * ADG_ERR_UNSUPPORTED).  Overwrites the face hull of the workspace. */
 adg_status adg_step_adjoint(adg_ctx* ctx, const double* d_Qn, const double* d_params,
                             const double* d_dt, double* d_Qbar, double* d_params_bar);
 

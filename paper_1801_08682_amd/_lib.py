@@ -27,7 +27,8 @@ class AdgConfig(ctypes.Structure):
                 ("pde", ctypes.c_int32),
                 ("pde_param", ctypes.c_double * 4),
                 ("picard_iters", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32),
+                ("adjoint", ctypes.c_int32)]
 
 
 class AdgError(RuntimeError):
@@ -80,7 +81,8 @@ def check(status, ctx=None):
         raise AdgError(status, msg)
 
 
-def make_config(dim, order, n_cells, length, pde, pde_param=(), picard_iters=0, precision=0):
+def make_config(dim, order, n_cells, length, pde, pde_param=(), picard_iters=0, precision=0,
+                adjoint=False):
     c = AdgConfig()
     c.dim = dim
     c.order = order
@@ -96,6 +98,7 @@ def make_config(dim, order, n_cells, length, pde, pde_param=(), picard_iters=0, 
         c.pde_param[i] = float(pp[i])
     c.picard_iters = picard_iters
     c.precision = precision
+    c.adjoint = 1 if adjoint else 0
     return c
 
 

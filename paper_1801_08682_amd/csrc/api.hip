@@ -19,9 +19,17 @@ thread_local std::string g_err;
 struct Layout {
   int64_t trace_off = 0, trace_bytes = 0;
   int64_t partial_off = 0, partial_count = 0;
-  int64_t scratch_off = 0, scratch_bytes = 0;
+  int64_t qtmp_off = 0, tb_off = 0, slots_off = 0, nslots = 0;
   int64_t total = 0;
 };
+
+// Per-block Picard scratch of the adjoint: at most 1024 blocks and 2 GiB.
+int64_t adjoint_slots(int64_t cells, int64_t slot_bytes) {
+  int64_t s = cells < 1024 ? cells : 1024;
+  const int64_t cap = (int64_t(2) << 30) / (slot_bytes > 0 ? slot_bytes : 1);
+  if (s > cap) s = cap > 1 ? cap : 1;
+  return s;
+}
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
@@ -45,6 +53,10 @@ adg_status validate(const adg_config* c, std::string* msg) {
   if (c->order < 0 || c->order > 15) { *msg = "order must be in [0, 15]"; return ADG_ERR_INVALID_ARG; }
   if (c->pde < 0 || c->pde > 3) { *msg = "unknown pde"; return ADG_ERR_INVALID_ARG; }
   if (c->precision < 0 || c->precision > 2) { *msg = "unknown precision"; return ADG_ERR_INVALID_ARG; }
+  if (c->adjoint != 0 && c->precision != ADG_FP64) {
+    *msg = "the adjoint needs precision ADG_FP64";
+    return ADG_ERR_UNSUPPORTED;
+  }
   if (c->picard_iters < 0 || c->picard_iters > 1000) {
     *msg = "picard_iters must be in [0, 1000]";
     return ADG_ERR_INVALID_ARG;
@@ -93,9 +105,16 @@ Layout layout_of(const adg_config* c, const adg::Launchers* L) {
   l.trace_bytes = align256(cells * L->trace_bytes_per_cell);
   l.partial_off = l.trace_off + l.trace_bytes;
   l.partial_count = adg::kMaxReduceBlocks;
-  l.scratch_off = l.partial_off + align256(l.partial_count * 8);
-  l.scratch_bytes = align256(cells * L->scratch_bytes_per_cell);
-  l.total = l.scratch_off + l.scratch_bytes;
+  l.total = l.partial_off + align256(l.partial_count * 8);
+  if (c->adjoint && L->adjoint) {
+    const int R = c->picard_iters > 0 ? c->picard_iters : c->order + 1;
+    const int64_t slot = L->adj_slot_doubles(R) * 8;
+    l.qtmp_off = l.total;
+    l.tb_off = l.qtmp_off + align256(cells * L->qdofs_per_cell * 8);
+    l.slots_off = l.tb_off + align256(cells * L->trace_bytes_per_cell);
+    l.nslots = adjoint_slots(cells, slot);
+    l.total = l.slots_off + align256(l.nslots * slot);
+  }
   return l;
 }
 
@@ -135,7 +154,12 @@ struct adg_ctx {
     a.partial = reinterpret_cast<double*>(ws + lay.partial_off);
     a.n_partial = lay.partial_count;
     a.n_partial_used = &n_partial_used;
-    a.scratch = ws + lay.scratch_off;
+    if (lay.nslots > 0) {
+      a.adj_qtmp = reinterpret_cast<double*>(ws + lay.qtmp_off);
+      a.adj_tb = reinterpret_cast<double*>(ws + lay.tb_off);
+      a.adj_slots = reinterpret_cast<double*>(ws + lay.slots_off);
+      a.adj_nslots = lay.nslots;
+    }
     a.ncells = ncells;
     for (int i = 0; i < 3; ++i) a.nc[i] = (i < cfg.dim) ? cfg.n_cells[i] : 1;
     a.inv_h = 1.0 / h;
@@ -288,7 +312,9 @@ adg_status adg_step_adjoint(adg_ctx* ctx, const double* d_Qn, const double* d_pa
   adg_status s = check_state(ctx, d_Qn, d_params, d_dt);
   if (s != ADG_OK) return s;
   if (!d_Qbar) return ctx->fail(ADG_ERR_INVALID_ARG, "Qbar is required");
-  if (!ctx->L->adjoint) return ctx->fail(ADG_ERR_UNSUPPORTED, "adjoint not compiled for this configuration");
+  if (!ctx->L->adjoint) return ctx->fail(ADG_ERR_UNSUPPORTED, "adjoint needs precision ADG_FP64");
+  if (ctx->lay.nslots <= 0)
+    return ctx->fail(ADG_ERR_WORKSPACE, "adjoint workspace not reserved (set adg_config.adjoint)");
   adg::LaunchArgs a = ctx->args();
   a.Qc = d_Qn;
   a.params = d_params;

@@ -85,7 +85,10 @@ struct LaunchArgs {
   double* params_bar = nullptr;     // adjoint accumulator
   int32_t* flag = nullptr;
   void* traces = nullptr;           // face hull
-  void* scratch = nullptr;          // adjoint scratch
+  double* adj_qtmp = nullptr;       // adjoint: copy of Q for the traces
+  double* adj_tb = nullptr;         // adjoint: trace bars
+  double* adj_slots = nullptr;      // adjoint: per-block Picard scratch
+  int64_t adj_nslots = 0;
   double* partial = nullptr;        // per-block maxima
   int64_t n_partial = 0;            // capacity of partial
   int64_t* n_partial_used = nullptr;// host-side record of the last count
@@ -106,7 +109,8 @@ struct Launchers {
   LaunchFn wave_speed = nullptr;
   LaunchFn adjoint = nullptr;
   int64_t trace_bytes_per_cell = 0;
-  int64_t scratch_bytes_per_cell = 0;
+  int64_t qdofs_per_cell = 0;                  // m (N+1)^d
+  int64_t (*adj_slot_doubles)(int R) = nullptr;
 };
 
 // Registries implemented by the per-PDE instantiation units.

@@ -582,6 +582,7 @@ Launchers make_fwd_launchers() {
   L.correct = &launch_correct<K>;
   L.wave_speed = &launch_wave_speed<K>;
   L.trace_bytes_per_cell = K::TRACE_ELEMS * (int64_t)sizeof(typename K::Real);
+  L.qdofs_per_cell = (int64_t)K::NS * K::M;
   return L;
 }
 

@@ -60,6 +60,16 @@ struct Advection {
   __device__ static inline bool admissible(const T* q, const Gconst<T>&, const CP<T>&) {
     return isfinite(q[0]);
   }
+  // Reverse mode: qb += (dF_I/dq)^T Fb ; pb += (dF_I/dpar)^T Fb
+  template <int I>
+  __device__ static inline void flux_adj(const double*, const double* Fb, double* qb, double*,
+                                         const Gconst<double>& g, const CP<double>&) {
+    qb[0] += g.c[I] * Fb[0];
+  }
+  // qb += sb dspeed_I/dq ; pb += sb dspeed_I/dpar
+  template <int I>
+  __device__ static inline void speed_adj(const double*, double, double*, double*,
+                                          const Gconst<double>&, const CP<double>&) {}
 };
 
 // g.c[0] = gamma, g.c[1] = gamma - 1
@@ -106,6 +116,62 @@ struct Euler {
     const T ir = rcp(q[0]);
     return q[0] > T(0) && pressure(q, ir, g) > T(0);
   }
+  // Reverse mode of flux_aux through ir = 1/rho, u_I = j_I ir,
+  // p = (gamma-1)(E - |j|^2 ir / 2).
+  template <int I>
+  __device__ static inline void flux_adj(const double* q, const double* Fb, double* qb, double*,
+                                         const Gconst<double>& g, const CP<double>&) {
+    const double ir = 1.0 / q[0];
+    const double p = pressure(q, ir, g);
+    const double uI = q[1 + I] * ir;
+    double uIb = 0.0, pb = 0.0, irb = 0.0;
+    qb[1 + I] += Fb[0];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      qb[1 + k] += Fb[1 + k] * uI;
+      uIb += Fb[1 + k] * q[1 + k];
+    }
+    pb += Fb[1 + I];
+    uIb += Fb[D + 1] * (q[D + 1] + p);
+    qb[D + 1] += Fb[D + 1] * uI;
+    pb += Fb[D + 1] * uI;
+    qb[1 + I] += uIb * ir;
+    irb += uIb * q[1 + I];
+    double jj = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      jj += q[1 + k] * q[1 + k];
+      qb[1 + k] += -g.c[1] * pb * q[1 + k] * ir;
+    }
+    qb[D + 1] += g.c[1] * pb;
+    irb += -g.c[1] * pb * 0.5 * jj;
+    qb[0] += -irb * ir * ir;
+  }
+  // Reverse mode of speed_I = |u_I| + sqrt(gamma p ir) (d|x|/dx = 0 at 0).
+  template <int I>
+  __device__ static inline void speed_adj(const double* q, double sb, double* qb, double*,
+                                          const Gconst<double>& g, const CP<double>&) {
+    const double ir = 1.0 / q[0];
+    const double p = pressure(q, ir, g);
+    const double uI = q[1 + I] * ir;
+    const double cs = sqrt(g.c[0] * p * ir);
+    const double sg = uI > 0.0 ? 1.0 : (uI < 0.0 ? -1.0 : 0.0);
+    double uIb = sb * sg;
+    const double xb = sb / (2.0 * cs);          // bar of gamma p ir
+    double pb = xb * g.c[0] * ir;
+    double irb = xb * g.c[0] * p;
+    qb[1 + I] += uIb * ir;
+    irb += uIb * q[1 + I];
+    double jj = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      jj += q[1 + k] * q[1 + k];
+      qb[1 + k] += -g.c[1] * pb * q[1 + k] * ir;
+    }
+    qb[D + 1] += g.c[1] * pb;
+    irb += -g.c[1] * pb * 0.5 * jj;
+    qb[0] += -irb * ir * ir;
+  }
 };
 
 // Per cell: par[0] = sound speed c (rho_0 = 1, bulk modulus c^2).
@@ -138,6 +204,19 @@ struct Acoustic {
 #pragma unroll
     for (int v = 0; v < M; ++v) ok = ok && isfinite(q[v]);
     return ok;
+  }
+  // F_I = (c^2 u_I, p e_I): pb[0] is the bar of the sound speed c.
+  template <int I>
+  __device__ static inline void flux_adj(const double* q, const double* Fb, double* qb, double* pb,
+                                         const Gconst<double>&, const CP<double>& cp) {
+    qb[1 + I] += cp.K * Fb[0];
+    qb[0] += Fb[1 + I];
+    pb[0] += 2.0 * cp.c * q[1 + I] * Fb[0];
+  }
+  template <int I>
+  __device__ static inline void speed_adj(const double*, double sb, double*, double* pb,
+                                          const Gconst<double>&, const CP<double>&) {
+    pb[0] += sb;
   }
 };
 
@@ -196,6 +275,33 @@ struct Elastic {
 #pragma unroll
     for (int v = 0; v < M; ++v) ok = ok && isfinite(q[v]);
     return ok;
+  }
+  // pb = bars of (rho, lambda, mu).
+  template <int I>
+  __device__ static inline void flux_adj(const double* q, const double* Fb, double* qb, double* pb,
+                                         const Gconst<double>&, const CP<double>& cp) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      qb[D + slot(I, k)] += -Fb[k] * cp.irho;
+      pb[0] += Fb[k] * q[D + slot(I, k)] * cp.irho * cp.irho;
+    }
+#pragma unroll
+    for (int s = 0; s < NS_; ++s) {
+      const int k = vk(s), l = vl(s);
+      const double fb = -Fb[D + s];
+      if (I == k) { qb[l] += cp.mu * fb; pb[2] += q[l] * fb; }
+      if (I == l) { qb[k] += cp.mu * fb; pb[2] += q[k] * fb; }
+      if (k == l) { qb[I] += cp.lam * fb; pb[1] += q[I] * fb; }
+    }
+  }
+  // speed = sqrt((lambda + 2 mu) / rho)
+  template <int I>
+  __device__ static inline void speed_adj(const double*, double sb, double*, double* pb,
+                                          const Gconst<double>&, const CP<double>& cp) {
+    const double x = 0.5 * sb / cp.cp;            // bar of (lambda + 2 mu) / rho
+    pb[1] += x * cp.irho;
+    pb[2] += 2.0 * x * cp.irho;
+    pb[0] += -x * cp.cp * cp.cp * cp.irho;
   }
 };
 

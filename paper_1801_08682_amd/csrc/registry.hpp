@@ -2,14 +2,20 @@
 // are instantiated.  Included by exactly one instantiation unit per PDE.
 #pragma once
 
-#include "kernels_fwd.hpp"
+#include "kernels_adj.hpp"
 
 namespace adg {
 
 template <template <int> class PDET, int D, int N>
 const Launchers* pick_precision(int prec) {
   if (prec == 0) {
-    static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, double>>();
+    using K = Fwd<D, N, PDET, double>;
+    static const Launchers L = [] {
+      Launchers l = make_fwd_launchers<K>();
+      l.adjoint = &launch_adjoint<K>;
+      l.adj_slot_doubles = [](int R) { return adj_slot_doubles<K>(R); };
+      return l;
+    }();
     return &L;
   }
   if (prec == 1) {
