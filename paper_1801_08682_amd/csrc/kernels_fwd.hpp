@@ -22,12 +22,27 @@
 #include "common.hpp"
 
 #ifndef ADG_PLANE_PAD
-#define ADG_PLANE_PAD 0
+#define ADG_PLANE_PAD 3
+#endif
+#ifndef ADG_SKEW_Z
+#define ADG_SKEW_Z 0
+#endif
+#ifndef ADG_TASK_TT_FAST
+#define ADG_TASK_TT_FAST 0
 #endif
 
 namespace adg {
 
 constexpr int PLANE_PAD = ADG_PLANE_PAD;
+constexpr int SKEW_Z = ADG_SKEW_Z;          // extra doubles between z-planes of a slice
+constexpr bool TASK_TT_FAST = ADG_TASK_TT_FAST;
+
+// LDS position of spatial node a inside one (slice, var) plane.
+template <int n, int D>
+__device__ __forceinline__ int lds_pos(int a) {
+  if constexpr (D == 3 && SKEW_Z > 0) return a + SKEW_Z * (a / (n * n));
+  else return a;
+}
 
 template <int D_, int N_, template <int> class PDET, class Real_>
 struct Fwd {
@@ -42,7 +57,7 @@ struct Fwd {
   static constexpr int THREADS = CPB * NS;
   // LDS plane stride (one time slice, one variable): NS plus padding that
   // shifts consecutive planes across the LDS banks
-  static constexpr int NSP = NS + PLANE_PAD;
+  static constexpr int NSP = NS + PLANE_PAD + (D == 3 ? SKEW_Z * (n - 1) : 0);
   static constexpr int LDS_BUDGET = 80 * 1024;
   static constexpr int SLICE_BYTES = 2 * NSP * M * (int)sizeof(Real);
   static constexpr int pick_S() {
@@ -50,9 +65,14 @@ struct Fwd {
       if (CPB * s * SLICE_BYTES <= LDS_BUDGET) return s;
     return 1;
   }
-  static constexpr int S = pick_S();
+  // ALIAS: one LDS buffer holds all n slices; every thread first contracts
+  // its pencils of all d axes into registers, then the axis sums overwrite
+  // the buffer in place (half the LDS of a separate rhs buffer).
+  static constexpr int FULL_BYTES = CPB * n * NSP * M * (int)sizeof(Real);
+  static constexpr bool ALIAS = 2 * FULL_BYTES > 32 * 1024 && FULL_BYTES <= 48 * 1024;
+  static constexpr int S = ALIAS ? n : pick_S();
   static constexpr int NB = (n + S - 1) / S;                 // batches per iteration
-  static constexpr int PIC_BYTES = 2 * S * NSP * M * (int)sizeof(Real);
+  static constexpr int PIC_BYTES = (ALIAS ? 1 : 2) * S * NSP * M * (int)sizeof(Real);
   static constexpr int FIN_BYTES = 3 * NS * M * 8;
   static constexpr int CELL_BYTES = ((PIC_BYTES > FIN_BYTES ? PIC_BYTES : FIN_BYTES) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
@@ -108,6 +128,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   for (int t = 0; t < n; ++t)
 #pragma unroll
     for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v];
+  const int pa = lds_pos<n, D>(a);
 
   // Node role: publish time slices [t0, t0 + ns) of this node's column.
   auto publish = [&](auto T0_, auto NS_) {
@@ -115,7 +136,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
 #pragma unroll
     for (int tt = 0; tt < ns; ++tt)
 #pragma unroll
-      for (int v = 0; v < M; ++v) Qs[(tt * M + v) * NSP + a] = q[t0 + tt][v];
+      for (int v = 0; v < M; ++v) Qs[(tt * M + v) * NSP + pa] = q[t0 + tt][v];
   };
   // Pencil role: for every published slice and axis I, evaluate F_I along a
   // pencil and contract with D; the three axis results are summed in Rs.
@@ -132,7 +153,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
           for (int v = 0; v < M; ++v) out[k][v] = Real(0);
 #pragma unroll
         for (int j = 0; j < n; ++j) {
-          const int nd = pencil_node<n, I>(b, j);
+          const int nd = lds_pos<n, D>(pencil_node<n, I>(b, j));
           Real qn[M], F[M];
 #pragma unroll
           for (int v = 0; v < M; ++v) qn[v] = qsl[v * NSP + nd];
@@ -145,7 +166,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
         Real* rsl = Rs + tt * M * NSP;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-          const int nd = pencil_node<n, I>(b, k);
+          const int nd = lds_pos<n, D>(pencil_node<n, I>(b, k));
 #pragma unroll
           for (int v = 0; v < M; ++v) {
             if constexpr (I == 0) rsl[v * NSP + nd] = out[k][v];
@@ -154,7 +175,8 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
         }
       };
       if constexpr (ns * NF == NS) {
-        pencil(a / NF, a % NF);                  // exactly one task per thread
+        if constexpr (TASK_TT_FAST) pencil(a % ns, a / ns);   // one task per thread
+        else pencil(a / NF, a % NF);
       } else {
         for (int task = a; task < ns * NF; task += NS) pencil(task / NF, task % NF);
       }
@@ -163,6 +185,85 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   };
 
   // ---- predict: Picard iteration q <- u - (dt/h) P sum_i D_i F_i(q) ----
+  if constexpr (K::ALIAS) {
+    // One pencil per axis per thread and slice: evaluate F_I along the
+    // pencil, contract with D, keep the result in registers.
+    auto pencils = [&](auto NS_, auto& out) {
+      constexpr int ns = decltype(NS_)::value;
+      const int tt = (ns * NF == NS) ? (TASK_TT_FAST ? a % ns : a / NF) : 0;
+      const int b = (ns * NF == NS) ? (TASK_TT_FAST ? a / ns : a % NF) : a;
+      const bool act = (ns * NF == NS) || a < NF;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+#pragma unroll
+          for (int v = 0; v < M; ++v) out[I][k][v] = Real(0);
+        if (act) {
+          const Real* qsl = Qs + tt * M * NSP;
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            const int nd = lds_pos<n, D>(pencil_node<n, I>(b, j));
+            Real qn[M], F[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) qn[v] = qsl[v * NSP + nd];
+            PDE::template flux<I>(qn, F, p.g, cp);
+#pragma unroll
+            for (int k = 0; k < n; ++k)
+#pragma unroll
+              for (int v = 0; v < M; ++v) out[I][k][v] = fma(p.t.D[k][j], F[v], out[I][k][v]);
+          }
+        }
+      });
+      __syncthreads();                              // all pencils read: reuse Qs as rhs
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        if (act) {
+          Real* rsl = Qs + tt * M * NSP;
+#pragma unroll
+          for (int k = 0; k < n; ++k) {
+            const int nd = lds_pos<n, D>(pencil_node<n, I>(b, k));
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+              if constexpr (I == 0) rsl[v * NSP + nd] = out[I][k][v];
+              else rsl[v * NSP + nd] += out[I][k][v];
+            }
+          }
+        }
+        __syncthreads();
+      });
+    };
+    Real out[D][n][M];
+    // first iteration: one slice (q = u on every slice)
+    publish(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+    __syncthreads();
+    pencils(std::integral_constant<int, 1>{}, out);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      const Real rv = Qs[v * NSP + pa];
+#pragma unroll
+      for (int t = 0; t < n; ++t) q[t][v] = (Real)u[v] - c * (p.t.Ps[t] * rv);
+    }
+    for (int r = 1; r < p.R; ++r) {
+      __syncthreads();                              // slice 0 read by every node above
+      publish(std::integral_constant<int, 0>{}, std::integral_constant<int, n>{});
+      __syncthreads();
+      pencils(std::integral_constant<int, n>{}, out);
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        Real rv[n];
+#pragma unroll
+        for (int tt = 0; tt < n; ++tt) rv[tt] = Qs[(tt * M + v) * NSP + pa];
+#pragma unroll
+        for (int t = 0; t < n; ++t) {
+          Real acc = Real(0);
+#pragma unroll
+          for (int tt = 0; tt < n; ++tt) acc = fma(p.t.P[t][tt], rv[tt], acc);
+          q[t][v] = (Real)u[v] - c * acc;
+        }
+      }
+    }
+  } else {
   // First iteration: q = u is constant in time, so sum_i D_i F_i(q) is the
   // same on every slice and P reduces to its row sums (one slice computed).
   publish(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
@@ -170,7 +271,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   contract(std::integral_constant<int, 1>{});
 #pragma unroll
   for (int v = 0; v < M; ++v) {
-    const Real rv = Rs[v * NSP + a];
+    const Real rv = Rs[v * NSP + pa];
 #pragma unroll
     for (int t = 0; t < n; ++t) q[t][v] = (Real)u[v] - c * (p.t.Ps[t] * rv);
   }
@@ -192,7 +293,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
       for (int tt = 0; tt < ns; ++tt)
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          const Real rv = Rs[(tt * M + v) * NSP + a];
+          const Real rv = Rs[(tt * M + v) * NSP + pa];
 #pragma unroll
           for (int t = 0; t < n; ++t) acc[t][v] = fma(p.t.P[t][t0 + tt], rv, acc[t][v]);
         }
@@ -202,6 +303,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
     for (int t = 0; t < n; ++t)
 #pragma unroll
       for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v] - c * acc[t][v];
+  }
   }
   __syncthreads();   // LDS is reused below
 
