@@ -340,51 +340,42 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
     }
     __syncthreads();
     for (int b = a; b < NF; b += NS) {
-      double vol[n][M], qL[M], qR[M], fL[M], fR[M];
+      Real* tr = p.tr + cs * K::TRACE_ELEMS;
+      Real* tL = tr + (int64_t)(2 * I) * K::NQ * NF * M + b * M;
+      Real* tR = tr + (int64_t)(2 * I + 1) * K::NQ * NF * M + b * M;
+      // one variable at a time keeps n + 4 doubles live
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        qL[v] = qR[v] = fL[v] = fR[v] = 0.0;
+        double fv[n], vol[n], qL = 0.0, qR = 0.0, fL = 0.0, fR = 0.0;
 #pragma unroll
-        for (int k = 0; k < n; ++k) vol[k][v] = 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < n; ++j) {
-        const int nd = pencil_node<n, I>(b, j);
-#pragma unroll
-        for (int v = 0; v < M; ++v) {
-          const double fv = Fb[v * NS + nd];
+        for (int j = 0; j < n; ++j) {
+          const int nd = pencil_node<n, I>(b, j);
+          fv[j] = Fb[v * NS + nd];
           const double qv = Qb[v * NS + nd];
-#pragma unroll
-          for (int k = 0; k < n; ++k) vol[k][v] += p.t.Kv[k][j] * fv;
-          qL[v] += p.t.FL[j] * qv;
-          qR[v] += p.t.FR[j] * qv;
-          fL[v] += p.t.FL[j] * fv;
-          fR[v] += p.t.FR[j] * fv;
+          qL += p.t.FL[j] * qv;
+          qR += p.t.FR[j] * qv;
+          fL += p.t.FL[j] * fv[j];
+          fR += p.t.FR[j] * fv[j];
         }
-      }
 #pragma unroll
-      for (int k = 0; k < n; ++k) {
-        const int nd = pencil_node<n, I>(b, k);
+        for (int k = 0; k < n; ++k) {
+          double sacc = 0.0;
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-          if constexpr (I == 0) Vs[v * NS + nd] = vol[k][v];
-          else Vs[v * NS + nd] += vol[k][v];
+          for (int j = 0; j < n; ++j) sacc += p.t.Kv[k][j] * fv[j];
+          vol[k] = sacc;
         }
-      }
-      if (live) {
-        Real* tr = p.tr + cell * K::TRACE_ELEMS;
-        Real* tL = tr + (int64_t)(2 * I) * K::NQ * NF * M + b * M;
-        Real* tR = tr + (int64_t)(2 * I + 1) * K::NQ * NF * M + b * M;
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-          tL[v] = (Real)qL[v];
-          tR[v] = (Real)qR[v];
+        for (int k = 0; k < n; ++k) {
+          const int nd = pencil_node<n, I>(b, k);
+          if constexpr (I == 0) Vs[v * NS + nd] = vol[k];
+          else Vs[v * NS + nd] += vol[k];
         }
-        if constexpr (K::NQ == 2) {
-#pragma unroll
-          for (int v = 0; v < M; ++v) {
-            tL[NF * M + v] = (Real)fL[v];
-            tR[NF * M + v] = (Real)fR[v];
+        if (live) {
+          tL[v] = (Real)qL;
+          tR[v] = (Real)qR;
+          if constexpr (K::NQ == 2) {
+            tL[NF * M + v] = (Real)fL;
+            tR[NF * M + v] = (Real)fR;
           }
         }
       }
