@@ -5,8 +5,9 @@ extrapolation, volume term), adg_correct (Rusanov, face lift, update, wave
 speeds) and adg_cfl_dt (device-side dt for the next step), on the headline
 workload: 3D compressible Euler, gamma = 1.4, N = 4 (5^3 Gauss-Legendre nodes
 per cell), 81^3 periodic cells on [0,1]^3, density 1 + 0.1 exp(-r^2/0.02),
-u = 0, p = 1, Rusanov flux, dt = 0.9 h / (3 (2N+1) lambda_max) recomputed on
-the device every step.  Inputs are synthetic and resident in HBM before the
+u = 0, p = 1, Rusanov flux, dt = 0.5625 h / (3 (2N+1) lambda_max)
+recomputed on the device every step (0.9 of the measured linear-stability
+limit of the N = 4 step).  Inputs are synthetic and resident in HBM before the
 timed region.
 
 Prints ONE JSON line.  Besides the float64 path (``value``) it times the
@@ -61,11 +62,11 @@ def cpu_baseline(args):
                          extra={"ic": "bump"})
     Q = torch.tensor(inputs.initial_state(wl))
     s = ostep.Setup(wl.pde, 3, 4, wl.n_cells, wl.h, wl.pde_param)
-    dt = ostep.cfl_dt(ostep.max_wave_speed(Q, None, s), 0.9, s)
+    dt = ostep.cfl_dt(ostep.max_wave_speed(Q, None, s), inputs.stable_cfl(4), s)
     Q = ostep.step(Q, None, dt, s)               # warm-up
     t0 = time.perf_counter()
     for _ in range(args.cpu_steps):
-        dt = ostep.cfl_dt(ostep.max_wave_speed(Q, None, s), 0.9, s)
+        dt = ostep.cfl_dt(ostep.max_wave_speed(Q, None, s), inputs.stable_cfl(4), s)
         Q = ostep.step(Q, None, dt, s)
     t = time.perf_counter() - t0
     return {"value": wl.ncells * wl.dofs_per_cell * args.cpu_steps / t,
@@ -73,6 +74,47 @@ def cpu_baseline(args):
             "sample": f"{k}^3-cell periodic grid of the same workload (Euler N=4, "
                       f"h=1/81, bump), {args.cpu_steps} steps after 1 warm-up, "
                       f"torch CPU float64 on {platform.processor() or 'host'}"}
+
+
+def adjoint_bench(args):
+    """C4 at full size: 3D acoustics N=3, 48^3 cells, per-cell sound speed,
+    200 steps, receiver misfit at 64 receivers, gradient by the checkpointed
+    rollout (adg_step forward, adg_step_adjoint backward, checkpoint every 20)."""
+    import torch
+    from paper_1801_08682_amd import inputs
+    from paper_1801_08682_amd.rollout import rollout, receiver_rows
+    from paper_1801_08682_amd.stepper import Stepper
+    wl = inputs.preset("C4")
+    steps, k = args.adj_steps, wl.extra["checkpoint"]
+    Q0 = torch.tensor(inputs.initial_state(wl), device="cuda")
+    c = torch.tensor(inputs.cell_params(wl, seed=0), device="cuda")
+    ctrue = torch.tensor(inputs.cell_params(wl, seed=2), device="cuda")
+    rc, rr = receiver_rows(wl, inputs.receivers(64, 3, seed=1))
+    rec = (torch.tensor(rc, device="cuda"), torch.tensor(rr, device="cuda"))
+    dt = wl.cfl * wl.h / (3 * (2 * wl.order + 1) * float(c.max()))
+    st = Stepper(wl, adjoint=True)
+    with torch.no_grad():
+        _, data = rollout(st, Q0, ctrue, steps, dt=dt, checkpoint_every=k, receivers=rec)
+    Q = Q0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.run(Q, c, steps, dt=dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    Qg = Q0.clone().requires_grad_(True)
+    cg = c.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, smp = rollout(st, Qg, cg, steps, dt=dt, checkpoint_every=k, receivers=rec)
+    J = 0.5 * ((smp - data) ** 2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    st.close()
+    return {"workload": f"3D acoustics N=3, 48^3 cells, {steps} steps, 64 receivers, "
+                        f"checkpoint every {k}", "forward_s": t_fwd,
+            "forward_plus_backward_s": t_fb, "ratio": t_fb / t_fwd, "J": float(J),
+            "grad_norm_p0": float(Qg.grad[..., 0].norm()), "grad_norm_c": float(cg.grad.norm())}
 
 
 def run_path(st, Q0, steps, warmup, cfl, torch):
@@ -118,6 +160,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -149,8 +193,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"3D compressible Euler N=4, {args.cells}^3 periodic cells "
-                               "on [0,1]^3, Gaussian density bump, Rusanov, CFL 0.9/(2N+1), "
-                               "dt recomputed on device each step",
+                               "on [0,1]^3, Gaussian density bump, Rusanov, dt = 0.5625 h/(3 (2N+1) "
+                               "lambda_max) recomputed on device each step (0.9 of the "
+                               "N=4 stability limit)",
                    "cells": wl.ncells, "dofs_per_cell": wl.dofs_per_cell,
                    "picard_iters": R, "precision": "fp64"},
         "kernel_ms": {"predict": pred, "correct": corr, "cfl_dt": dtk},
@@ -183,6 +228,9 @@ def main():
                                    "(parity-checked against the oracle); absolute L2 for "
                                    "fields with negligible norm (momentum)"}
         st32.close()
+    if not args.no_adjoint:
+        print("[bench] adjoint (C4 misfit gradient)", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_bench(args)
     if args.copy_calib_mb:
         nbytes = args.copy_calib_mb << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")

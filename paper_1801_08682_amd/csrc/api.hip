@@ -23,9 +23,9 @@ struct Layout {
   int64_t total = 0;
 };
 
-// Per-block Picard scratch of the adjoint: at most 1024 blocks and 2 GiB.
+// Per-block Picard scratch of the adjoint: at most 16384 blocks and 2 GiB.
 int64_t adjoint_slots(int64_t cells, int64_t slot_bytes) {
-  int64_t s = cells < 1024 ? cells : 1024;
+  int64_t s = cells < 16384 ? cells : 16384;
   const int64_t cap = (int64_t(2) << 30) / (slot_bytes > 0 ? slot_bytes : 1);
   if (s > cap) s = cap > 1 ? cap : 1;
   return s;
@@ -104,7 +104,9 @@ Layout layout_of(const adg_config* c, const adg::Launchers* L) {
   l.trace_off = 0;
   l.trace_bytes = align256(cells * L->trace_bytes_per_cell);
   l.partial_off = l.trace_off + l.trace_bytes;
-  l.partial_count = adg::kMaxReduceBlocks;
+  // one maximum per corrector workgroup (padded to 8) or per reduction block
+  // plus 256 slots for the first stage of the dt reduction
+  l.partial_count = (cells + 64 > adg::kMaxReduceBlocks ? cells + 64 : adg::kMaxReduceBlocks) + 256;
   l.total = l.partial_off + align256(l.partial_count * 8);
   if (c->adjoint && L->adjoint) {
     const int R = c->picard_iters > 0 ? c->picard_iters : c->order + 1;
@@ -119,6 +121,16 @@ Layout layout_of(const adg_config* c, const adg::Launchers* L) {
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// First stage of the global maximum: 256 blocks, one maximum each.
+__global__ void __launch_bounds__(256) k_max256(const double* partial, int64_t cnt, double* out) {
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < cnt; k += 256 * 256)
+    m = fmax(m, partial[k]);
+  m = adg::block_max<256>(m, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = m;
+}
 
 __global__ void __launch_bounds__(256) k_dt(const double* partial, int64_t cnt, double coef,
                                             double* lam_out, double* dt_out) {
@@ -152,7 +164,7 @@ struct adg_ctx {
     adg::LaunchArgs a;
     a.traces = ws + lay.trace_off;
     a.partial = reinterpret_cast<double*>(ws + lay.partial_off);
-    a.n_partial = lay.partial_count;
+    a.n_partial = lay.partial_count - 256;   // the last 256 slots stage the dt reduction
     a.n_partial_used = &n_partial_used;
     if (lay.nslots > 0) {
       a.adj_qtmp = reinterpret_cast<double*>(ws + lay.qtmp_off);
@@ -161,7 +173,13 @@ struct adg_ctx {
       a.adj_nslots = lay.nslots;
     }
     a.ncells = ncells;
-    for (int i = 0; i < 3; ++i) a.nc[i] = (i < cfg.dim) ? cfg.n_cells[i] : 1;
+    for (int i = 0; i < 3; ++i) {
+      a.nc[i] = (i < cfg.dim) ? cfg.n_cells[i] : 1;
+      int b = 1;                      // largest divisor of the axis length up to 16
+      for (int d = 16; d >= 1; --d)
+        if (a.nc[i] % d == 0) { b = d; break; }
+      a.brick[i] = b;
+    }
     a.inv_h = 1.0 / h;
     a.R = R;
     for (int k = 0; k < 4; ++k) a.gp[k] = gp[k];
@@ -301,9 +319,15 @@ adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_
   if (ctx->n_partial_used <= 0)
     return ctx->fail(ADG_ERR_INVALID_ARG, "no wave speeds recorded (call adg_correct or adg_wave_speed)");
   const double coef = cfl * ctx->h / (ctx->cfg.dim * (2.0 * ctx->cfg.order + 1.0));
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream,
-                     reinterpret_cast<const double*>(ctx->ws + ctx->lay.partial_off), ctx->n_partial_used,
-                     coef, d_lambda_max, d_dt);
+  const double* part = reinterpret_cast<const double*>(ctx->ws + ctx->lay.partial_off);
+  int64_t cnt = ctx->n_partial_used;
+  if (cnt > 4096) {
+    double* stage = reinterpret_cast<double*>(ctx->ws + ctx->lay.partial_off) + ctx->lay.partial_count - 256;
+    hipLaunchKernelGGL(k_max256, dim3(256), dim3(256), 0, ctx->stream, part, cnt, stage);
+    part = stage;
+    cnt = 256;
+  }
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, part, cnt, coef, d_lambda_max, d_dt);
   return ctx->launched((int)hipGetLastError(), "cfl_dt");
 }
 

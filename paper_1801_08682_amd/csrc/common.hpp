@@ -94,6 +94,7 @@ struct LaunchArgs {
   int64_t* n_partial_used = nullptr;// host-side record of the last count
   int64_t ncells = 0;
   int nc[3] = {1, 1, 1};
+  int brick[3] = {1, 1, 1};         // brick walk of the corrector
   double inv_h = 1.0;
   int R = 1;
   double gp[4] = {0, 0, 0, 0};      // global PDE constants (see pde.hpp)

@@ -175,9 +175,12 @@ struct AdjPredP {
 
 template <class K>
 constexpr int64_t adj_slot_doubles(int R) {
-  return (int64_t)((R + 1) + K::D + 1) * K::n * K::M * K::NS;
+  // iterates q^0..q^R, fluxes of one iterate (d levels), rhs bar, iterate bar
+  return (int64_t)((R + 1) + K::D + 2) * K::n * K::M * K::NS;
 }
 
+// One thread per spatial node; every space-time array lives in the block's
+// scratch slot (L1/L2 resident) and each thread keeps only m-vectors.
 template <class K>
 __global__ void __launch_bounds__(K::NS) k_adj_pred(const AdjPredP<K> p) {
   using PDE = typename K::PDE;
@@ -188,179 +191,157 @@ __global__ void __launch_bounds__(K::NS) k_adj_pred(const AdjPredP<K> p) {
   double* QI = p.scratch + (int64_t)blockIdx.x * p.slot_doubles;   // [R+1][n][M][NS]
   double* FS = QI + (int64_t)(p.R + 1) * PL;                         // [D][n][M][NS]
   double* RB = FS + (int64_t)D * PL;                                 // [n][M][NS]
+  double* QB = RB + PL;                                              // [n][M][NS]
   const double c = (*p.dt) * p.inv_h;
-  auto at = [&](double* base, int tt, int v, int nd) -> double& { return base[(tt * M + v) * NS + nd]; };
+  auto at = [](double* base, int tt, int v, int nd) -> double& { return base[(tt * M + v) * NS + nd]; };
 
   for (int64_t cell = blockIdx.x; cell < p.ncells; cell += gridDim.x) {
-    double u[M], G[M];
+    double u[M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) {
-      u[v] = p.Q[(cell * NS + a) * M + v];
-      G[v] = p.Qbar[(cell * NS + a) * M + v];
-    }
+    for (int v = 0; v < M; ++v) u[v] = p.Q[(cell * NS + a) * M + v];
     const auto cp = PDE::template cell<double>(p.par + cell * NPAR);
     double pb[NPAR > 0 ? NPAR : 1];
 #pragma unroll
     for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
 
     // ---- recompute the Picard iterates (full iterations) ----
-    {
-      double q[n][M];
+    for (int tt = 0; tt < n; ++tt)
 #pragma unroll
-      for (int tt = 0; tt < n; ++tt)
+      for (int v = 0; v < M; ++v) at(QI, tt, v, a) = u[v];
+    for (int r = 1; r <= p.R; ++r) {
+      const double* Qp = QI + (int64_t)(r - 1) * PL;
+      for (int tt = 0; tt < n; ++tt) {
+        double q[M];
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-          q[tt][v] = u[v];
-          at(QI, tt, v, a) = u[v];
-        }
-      for (int r = 1; r <= p.R; ++r) {
+        for (int v = 0; v < M; ++v) q[v] = Qp[(tt * M + v) * NS + a];
         static_for<0, D>([&](auto I_) {
           constexpr int I = decltype(I_)::value;
+          double F[M];
+          PDE::template flux<I>(q, F, p.g, cp);
 #pragma unroll
-          for (int tt = 0; tt < n; ++tt) {
-            double F[M];
-            PDE::template flux<I>(q[tt], F, p.g, cp);
-#pragma unroll
-            for (int v = 0; v < M; ++v) at(FS + I * PL, tt, v, a) = F[v];
-          }
+          for (int v = 0; v < M; ++v) at(FS + I * PL, tt, v, a) = F[v];
         });
-        __syncthreads();
-        double rhs[n][M];
+      }
+      __syncthreads();
+      for (int tt = 0; tt < n; ++tt) {
+        double rhs[M];
 #pragma unroll
-        for (int tt = 0; tt < n; ++tt)
-#pragma unroll
-          for (int v = 0; v < M; ++v) rhs[tt][v] = 0.0;
+        for (int v = 0; v < M; ++v) rhs[v] = 0.0;
         static_for<0, D>([&](auto I_) {
           constexpr int I = decltype(I_)::value;
           const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
-#pragma unroll
           for (int j = 0; j < n; ++j) {
             const int nd = pencil_node<n, I>(fb, j);
             const double dj = p.t.D[ai][j];
 #pragma unroll
-            for (int tt = 0; tt < n; ++tt)
-#pragma unroll
-              for (int v = 0; v < M; ++v) rhs[tt][v] += dj * at(FS + I * PL, tt, v, nd);
+            for (int v = 0; v < M; ++v) rhs[v] += dj * at(FS + I * PL, tt, v, nd);
           }
         });
 #pragma unroll
-        for (int tt = 0; tt < n; ++tt)
-#pragma unroll
-          for (int v = 0; v < M; ++v) {
-            double s = 0.0;
-#pragma unroll
-            for (int l = 0; l < n; ++l) s += p.t.P[tt][l] * rhs[l][v];
-            q[tt][v] = u[v] - c * s;
-            at(QI + (int64_t)r * PL, tt, v, a) = q[tt][v];
-          }
-        __syncthreads();
+        for (int v = 0; v < M; ++v) at(RB, tt, v, a) = rhs[v];
       }
+      double* Qr = QI + (int64_t)r * PL;
+      for (int tt = 0; tt < n; ++tt)
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          double s = 0.0;
+          for (int l = 0; l < n; ++l) s += p.t.P[tt][l] * at(RB, l, v, a);
+          Qr[(tt * M + v) * NS + a] = u[v] - c * s;
+        }
+      __syncthreads();
     }
 
     // ---- bars of qbar and Fbar_i at this node ----
-    double qbb[M];
+    const double* TB = p.tb + cell * K::TRACE_ELEMS;
+    const double* Gc = p.Qbar + cell * NS * M;
+    double qbb[M], Fbb[D][M];
 #pragma unroll
     for (int v = 0; v < M; ++v) qbb[v] = 0.0;
-    double qb[n][M];                       // bar of the current iterate
-    const double* TB = p.tb + cell * K::TRACE_ELEMS;
     static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
       const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
       const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb * M;
       const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb * M;
 #pragma unroll
-      for (int v = 0; v < M; ++v) qbb[v] += p.t.FL[ai] * tl[v] + p.t.FR[ai] * trr[v];
-    });
-#pragma unroll
-    for (int tt = 0; tt < n; ++tt)
-#pragma unroll
-      for (int v = 0; v < M; ++v) qb[tt][v] = p.t.w[tt] * qbb[v];
-    static_for<0, D>([&](auto I_) {
-      constexpr int I = decltype(I_)::value;
-      const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
-      double Fbb[M];
-#pragma unroll
-      for (int v = 0; v < M; ++v) Fbb[v] = 0.0;
-      if constexpr (K::NQ == 2) {
-        const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + NF * M + fb * M;
-        const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + NF * M + fb * M;
-#pragma unroll
-        for (int v = 0; v < M; ++v) Fbb[v] += p.t.FL[ai] * tl[v] + p.t.FR[ai] * trr[v];
+      for (int v = 0; v < M; ++v) {
+        qbb[v] += p.t.FL[ai] * tl[v] + p.t.FR[ai] * trr[v];
+        Fbb[I][v] = (K::NQ == 2) ? p.t.FL[ai] * tl[NF * M + v] + p.t.FR[ai] * trr[NF * M + v] : 0.0;
       }
-      const double* Gc = p.Qbar + cell * NS * M;
-#pragma unroll
       for (int k = 0; k < n; ++k) {
         const int nd = pencil_node<n, I>(fb, k);
         const double kv = c * p.t.Kv[k][ai];
 #pragma unroll
-        for (int v = 0; v < M; ++v) Fbb[v] += kv * Gc[nd * M + v];
-      }
-#pragma unroll
-      for (int tt = 0; tt < n; ++tt) {
-        double q[M], fw[M];
-#pragma unroll
-        for (int v = 0; v < M; ++v) {
-          q[v] = at(QI + (int64_t)p.R * PL, tt, v, a);
-          fw[v] = p.t.w[tt] * Fbb[v];
-        }
-        PDE::template flux_adj<I>(q, fw, qb[tt], pb, p.g, cp);
+        for (int v = 0; v < M; ++v) Fbb[I][v] += kv * Gc[nd * M + v];
       }
     });
+    {
+      const double* QR = QI + (int64_t)p.R * PL;
+      for (int tt = 0; tt < n; ++tt) {
+        double q[M], acc[M];
+        const double wt = p.t.w[tt];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          q[v] = QR[(tt * M + v) * NS + a];
+          acc[v] = wt * qbb[v];
+        }
+        static_for<0, D>([&](auto I_) {
+          constexpr int I = decltype(I_)::value;
+          double fw[M];
+#pragma unroll
+          for (int v = 0; v < M; ++v) fw[v] = wt * Fbb[I][v];
+          PDE::template flux_adj<I>(q, fw, acc, pb, p.g, cp);
+        });
+#pragma unroll
+        for (int v = 0; v < M; ++v) at(QB, tt, v, a) = acc[v];
+      }
+    }
 
     // ---- reverse sweep over the Picard iterations ----
     double ub[M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) ub[v] = G[v];
+    for (int v = 0; v < M; ++v) ub[v] = Gc[a * M + v];
     for (int r = p.R; r >= 1; --r) {
+      for (int l = 0; l < n; ++l)
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-#pragma unroll
-        for (int tt = 0; tt < n; ++tt) ub[v] += qb[tt][v];
-#pragma unroll
-        for (int l = 0; l < n; ++l) {
+        for (int v = 0; v < M; ++v) {
           double s = 0.0;
-#pragma unroll
-          for (int tt = 0; tt < n; ++tt) s += p.t.P[tt][l] * qb[tt][v];
+          for (int tt = 0; tt < n; ++tt) s += p.t.P[tt][l] * at(QB, tt, v, a);
           at(RB, l, v, a) = -c * s;
         }
-      }
+#pragma unroll
+      for (int v = 0; v < M; ++v)
+        for (int tt = 0; tt < n; ++tt) ub[v] += at(QB, tt, v, a);
       __syncthreads();
-      double nb[n][M];
+      const double* Qp = QI + (int64_t)(r - 1) * PL;
+      for (int tt = 0; tt < n; ++tt) {
+        double q[M], nb[M];
 #pragma unroll
-      for (int tt = 0; tt < n; ++tt)
+        for (int v = 0; v < M; ++v) {
+          q[v] = Qp[(tt * M + v) * NS + a];
+          nb[v] = 0.0;
+        }
+        static_for<0, D>([&](auto I_) {
+          constexpr int I = decltype(I_)::value;
+          const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
+          double Fi[M];
 #pragma unroll
-        for (int v = 0; v < M; ++v) nb[tt][v] = 0.0;
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
-#pragma unroll
-        for (int tt = 0; tt < n; ++tt) {
-          double Fi[M], q[M];
-#pragma unroll
-          for (int v = 0; v < M; ++v) {
-            Fi[v] = 0.0;
-            q[v] = at(QI + (int64_t)(r - 1) * PL, tt, v, a);
-          }
-#pragma unroll
+          for (int v = 0; v < M; ++v) Fi[v] = 0.0;
           for (int k = 0; k < n; ++k) {
             const int nd = pencil_node<n, I>(fb, k);
             const double dk = p.t.D[k][ai];
 #pragma unroll
             for (int v = 0; v < M; ++v) Fi[v] += dk * at(RB, tt, v, nd);
           }
-          PDE::template flux_adj<I>(q, Fi, nb[tt], pb, p.g, cp);
-        }
-      });
+          PDE::template flux_adj<I>(q, Fi, nb, pb, p.g, cp);
+        });
 #pragma unroll
-      for (int tt = 0; tt < n; ++tt)
-#pragma unroll
-        for (int v = 0; v < M; ++v) qb[tt][v] = nb[tt][v];
+        for (int v = 0; v < M; ++v) at(QB, tt, v, a) = nb[v];
+      }
       __syncthreads();
     }
 #pragma unroll
     for (int v = 0; v < M; ++v)
-#pragma unroll
-      for (int tt = 0; tt < n; ++tt) ub[v] += qb[tt][v];
+      for (int tt = 0; tt < n; ++tt) ub[v] += at(QB, tt, v, a);
     __syncthreads();                       // every read of this cell's G is done
 #pragma unroll
     for (int v = 0; v < M; ++v) p.Qbar[(cell * NS + a) * M + v] = ub[v];

@@ -438,10 +438,30 @@ struct CorrP {
   int32_t* flag;
   int64_t ncells;
   int nc[3];
+  int brick[3];
   double inv_h;
   Gconst<double> g;
   double LL[K::n], LR[K::n];
 };
+
+// Cell visited at position g of a brick-major walk of the grid (bricks of
+// brick[0] x brick[1] x brick[2] cells, each dividing the grid).
+__device__ __forceinline__ int64_t brick_cell(int64_t g, const int* nc, const int* br) {
+  const int64_t bs = (int64_t)br[0] * br[1] * br[2];
+  const int64_t bi = g / bs, l = g - bi * bs;
+  const int64_t nbx = nc[0] / br[0], nby = nc[1] / br[1];
+  const int64_t bx = bi % nbx, by = (bi / nbx) % nby, bz = bi / (nbx * nby);
+  const int64_t lx = l % br[0], ly = (l / br[0]) % br[1], lz = l / ((int64_t)br[0] * br[1]);
+  return (bx * br[0] + lx) + nc[0] * ((by * br[1] + ly) + (int64_t)nc[1] * (bz * br[2] + lz));
+}
+
+// One cell group per workgroup.  Workgroup k runs on XCD k mod 8; each XCD
+// takes one contiguous eighth of the walk in dispatch order, so the traces
+// of recently corrected neighbours are still in its L2.
+__device__ __forceinline__ int64_t xcd_group(int64_t groups) {
+  const int64_t span = (groups + 7) / 8;
+  return (int64_t)(blockIdx.x % 8) * span + blockIdx.x / 8;
+}
 
 template <class K>
 __device__ __forceinline__ int64_t neighbour(int64_t cell, int i, int dir, const int* nc) {
@@ -473,9 +493,11 @@ __global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
   double lmax = 0.0;
   int bad = 0;
 
-  for (GroupIter it(groups); it.g < it.end; it.g += it.step) {
-    const int64_t cell = it.g * K::CCPB + lc;
-    const bool live = cell < p.ncells;
+  const int64_t grp = xcd_group(groups);
+  if (grp < groups) {
+    const int64_t gc = grp * K::CCPB + lc;
+    const bool live = gc < p.ncells;
+    const int64_t cell = live ? brick_cell(gc, p.nc, p.brick) : 0;
     // -- solveRiemann on the 2d faces: one thread per (face, face node) --
     double fh[M], dq[M];
     const bool ftask = live && t < K::FT;
@@ -563,7 +585,6 @@ __global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
         bad |= fin ? 2 : 1;
       }
     }
-    __syncthreads();
   }
   const double bm = block_max<K::CTHREADS>(lmax, red);
   if (threadIdx.x == 0) p.partial[blockIdx.x] = bm;
@@ -644,8 +665,9 @@ int launch_correct(const LaunchArgs& a) {
     p.LL[k] = a.tab->LL[k];
     p.LR[k] = a.tab->LR[k];
   }
+  for (int k = 0; k < 3; ++k) p.brick[k] = a.brick[k];
   const int64_t groups = (a.ncells + K::CCPB - 1) / K::CCPB;
-  const int64_t G = reduce_grid<K>(groups);
+  const int64_t G = 8 * ((groups + 7) / 8);
   if (G > a.n_partial) return (int)hipErrorInvalidValue;
   *a.n_partial_used = G;
   hipLaunchKernelGGL(k_corr<K>, dim3((unsigned)G), dim3(K::CTHREADS), 0, a.stream, p);
