@@ -47,9 +47,26 @@ def pred_flops_per_cell(d, n, m, R, cF):
 
 def corr_bytes_per_cell(d, n, m, real_bytes):
     """Algorithmic HBM bytes of one adg_correct per cell: read Q~ and write Q
-    (2 m n^d float64), read the cell's own 2d face traces and the 2d
-    neighbour traces once each (2 x 2d x 2 x m n^(d-1) values)."""
-    return 2 * m * n ** d * 8 + 2 * 2 * d * 2 * m * n ** (d - 1) * real_bytes
+    (2 m n^d float64) and read the face hull once (2d faces x 2 quantities x
+    m n^(d-1) values); a neighbour's traces re-read from HBM are waste."""
+    return 2 * m * n ** d * 8 + 2 * d * 2 * m * n ** (d - 1) * real_bytes
+
+
+def measured_traffic(key):
+    """Calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch recorded
+    in profiles/, valid only while the kernel sources hash the same."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_euler3d_n4_81cubed.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"] or key not in rec:
+        return None
+    return rec[key]["hbm_bytes"]
 
 
 def cpu_baseline(args):
@@ -202,10 +219,16 @@ def main():
         "cell_updates_per_s": wl.ncells * args.steps / wall,
         "roofline": {"kernel": "k_pred (adg_predict)", "bound": "alu", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic("k_pred_fp64") if args.cells == 81 else None,
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": wl.ncells * (wl.dofs_per_cell * 8 * 2
+                                                       + 2 * d * 2 * m * n ** (d - 1) * 8),
                      "flops_per_cell": fpc},
         "correct_hbm": {"achieved_GBps": corr_bytes_per_cell(d, n, m, 8) * wl.ncells
-                        / (corr * 1e-3) / 1e9, "peak_GBps": 8000.0},
+                        / (corr * 1e-3) / 1e9, "peak_GBps": 8000.0,
+                        "algorithmic_bytes": corr_bytes_per_cell(d, n, m, 8) * wl.ncells,
+                        "traffic": measured_traffic("k_corr_fp64") if args.cells == 81 else None},
     }
     st.close()
     del st
