@@ -134,6 +134,59 @@ def adjoint_bench(args):
             "grad_norm_p0": float(Qg.grad[..., 0].norm()), "grad_norm_c": float(cg.grad.norm())}
 
 
+def other_workload(args, torch):
+    """One line for a non-headline workload: float64 and float-predictor
+    throughput over its step count and the float path's per-field L2
+    difference to the float64 path at the end."""
+    from paper_1801_08682_amd import inputs
+    from paper_1801_08682_amd.stepper import Stepper
+    wl = inputs.preset(args.workload)
+    steps = wl.steps if args.steps == 100 else args.steps
+    Q0 = torch.tensor(inputs.initial_state(wl, seed=0), device="cuda")
+    par = inputs.cell_params(wl, seed=0)
+    par = None if par is None else torch.tensor(par, device="cuda")
+    res, states = {}, {}
+    for prec in (inputs.FP64, inputs.FP32):
+        st = Stepper(wl.with_(precision=prec))
+        if wl.adaptive_dt:
+            lam = None
+            cfl, dt = wl.cfl, None
+        else:
+            speed = 1.0 if wl.pde == inputs.ADVECTION else float(
+                (par[:, 0] if wl.pde == inputs.ACOUSTIC else
+                 torch.sqrt((par[:, 1] + 2 * par[:, 2]) / par[:, 0])).max())
+            cfl, dt = None, wl.cfl * wl.h / (wl.dim * (2 * wl.order + 1) * speed)
+        Q = Q0.clone()
+        st.run(Q, par, 2, cfl=cfl, dt=dt)          # warm-up on a copy
+        Q = Q0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.run(Q, par, steps, cfl=cfl, dt=dt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[prec] = {"value": wl.ncells * wl.dofs_per_cell * steps / wall,
+                     "ms_per_step": wall * 1e3 / steps}
+        states[prec] = Q
+        st.close()
+    n = wl.n
+    z, om = np.polynomial.legendre.leggauss(n)
+    w = torch.tensor(0.5 * om, device="cuda")
+    W = w
+    for _ in range(wl.dim - 1):
+        W = torch.kron(w, W)
+    ref, got = states[inputs.FP64], states[inputs.FP32]
+    norms = [float(torch.sqrt((W * ref[..., v] ** 2).sum())) for v in range(wl.m)]
+    err = []
+    for v in range(wl.m):
+        e = float(torch.sqrt((W * (got[..., v] - ref[..., v]) ** 2).sum()))
+        err.append(e / norms[v] if norms[v] > 1e-8 * max(norms) else e)
+    return {"metric": "DoF-updates/s", "unit": "DoF-updates/s", "workload": wl.name,
+            "config": {"pde": wl.pde, "dim": wl.dim, "order": wl.order, "cells": wl.ncells,
+                       "steps": steps, "cfl": wl.cfl},
+            "fp64": res[inputs.FP64], "fp32_predictor": res[inputs.FP32],
+            "fp32_rel_l2_vs_fp64_per_field": err}
+
+
 def run_path(st, Q0, steps, warmup, cfl, torch):
     """Warm-up on a copy, then `steps` timed steps; per-kernel event times."""
     Q = Q0.clone()
@@ -179,6 +232,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"],
+                    help="C2 is the headline line; the others print their own line "
+                         "(float64 and float-predictor throughput and per-field error)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -191,6 +247,9 @@ def main():
     from paper_1801_08682_amd import inputs
     from paper_1801_08682_amd.stepper import Stepper
 
+    if args.workload != "C2":
+        print(json.dumps(other_workload(args, torch)), flush=True)
+        return
     wl = inputs.preset("C2").with_(n_cells=(args.cells,) * 3,
                                    length=args.cells / 81.0)
     d, n, m = wl.dim, wl.n, wl.m
