@@ -86,7 +86,7 @@ typedef struct adg_ctx adg_ctx;
  *                     extrapolate, reduced to one time value per face node)
  *                     plus reduction scratch; with cfg->adjoint also a copy
  *                     of Q, the hull's bars and per-block Picard scratch
- *                     (at most 16384 blocks, at most 2 GiB).
+ *                     (at most 2048 blocks, at most 2 GiB).
  * Any output pointer may be NULL.  Returns INVALID_ARG / UNSUPPORTED as above. */
 adg_status adg_query(const adg_config* cfg, int64_t* dofs_per_cell, int64_t* params_per_cell,
                      int64_t* workspace_bytes);

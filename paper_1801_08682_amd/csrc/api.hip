@@ -23,9 +23,9 @@ struct Layout {
   int64_t total = 0;
 };
 
-// Per-block Picard scratch of the adjoint: at most 16384 blocks and 2 GiB.
+// Per-block Picard scratch of the adjoint: at most 2048 blocks and 2 GiB.
 int64_t adjoint_slots(int64_t cells, int64_t slot_bytes) {
-  int64_t s = cells < 16384 ? cells : 16384;
+  int64_t s = cells < 2048 ? cells : 2048;
   const int64_t cap = (int64_t(2) << 30) / (slot_bytes > 0 ? slot_bytes : 1);
   if (s > cap) s = cap > 1 ? cap : 1;
   return s;

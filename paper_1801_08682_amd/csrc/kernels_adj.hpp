@@ -11,9 +11,10 @@
 //              first), written as this cell's own trace bars.  Both cells of
 //              a face compute the face quantities identically; each writes
 //              only its own bars and material bars (no atomics).
-//  k_adj_pred  per cell: recompute the Picard iterates q^0..q^R into a
-//              per-block scratch slot, map the trace bars and Kv^T G back to
-//              bars of (qbar, Fbar_i), then sweep the iterations backwards:
+//  k_adj_pred  per cell: recompute the Picard iterates (q^1..q^{R-1} kept
+//              in a per-block scratch slot, time columns in registers,
+//              pencils in LDS), map the trace bars and Kv^T G back to bars of
+//              (qbar, Fbar_i), then sweep the iterations backwards:
 //              rhs bar = -(dt/h) P^T qb, F_i bar = D_i^T rhs bar,
 //              q^{r-1} bar = sum_i J_i(q^{r-1})^T F_i bar, u bar += sum_t q^r bar.
 #pragma once
@@ -164,7 +165,7 @@ struct AdjPredP {
   double* Qbar;          // in: dJ/dQ+, out: dJ/dQ
   const double* tb;      // trace bars
   double* pbar;
-  double* scratch;       // per-block slots
+  double* scratch;       // per-block slots of stored Picard iterates
   int64_t slot_doubles;
   int64_t ncells;
   double inv_h;
@@ -173,189 +174,320 @@ struct AdjPredP {
   KTab<K::n, double> t;
 };
 
+// LDS plan of the adjoint predictor: two node-major buffers of S time slices
+// per cell (published values, pencil results), S as large as 80 KiB allows.
+template <class K>
+struct AdjPlan {
+  static constexpr int SL = K::NSP * K::MP;                 // doubles per slice
+  static constexpr int pick_S() {
+    for (int s = K::n; s > 1; --s)
+      if (K::CPB * 2 * s * SL * 8 <= 80 * 1024) return s;
+    return 1;
+  }
+  static constexpr int S = pick_S();
+  static constexpr int NB = (K::n + S - 1) / S;
+  static constexpr int CELL = 2 * S * SL;                   // doubles per cell
+};
+
+// Stored iterates q^1 .. q^{R-1} of the CPB cells of a block:
+// [r-1][t][v][CPB * NS], node fastest (coalesced per thread).
 template <class K>
 constexpr int64_t adj_slot_doubles(int R) {
-  // iterates q^0..q^R, fluxes of one iterate (d levels), rhs bar, iterate bar
-  return (int64_t)((R + 1) + K::D + 2) * K::n * K::M * K::NS;
+  const int64_t levels = R > 2 ? R - 1 : 1;
+  return levels * K::n * K::M * K::NS * K::CPB;
 }
 
-// One thread per spatial node; every space-time array lives in the block's
-// scratch slot (L1/L2 resident) and each thread keeps only m-vectors.
+// One thread per spatial node, CPB cells per workgroup, one cell per thread
+// group at a time (persistent blocks, each with its scratch slot).  The
+// node thread keeps time columns in registers; spatial contractions go
+// through LDS pencils exactly as in the forward predictor.
+//  1. recompute q^1..q^R (first iteration on one slice), storing q^1..q^{R-1};
+//  2. bars of the time averages: qbar from the q traces, Fbar_i from the flux
+//     traces and the volume term (Kv^T of G), then q^R bar at every time node;
+//  3. for r = R..1: u bar += sum_t q^r bar; rhs bar = -(dt/h) P^T q^r bar;
+//     F_i bar = D_i^T rhs bar (pencils), q^{r-1} bar = sum_i J_i(q^{r-1})^T F_i bar
+//     (r = 1: one slice with the row sums of P, q^0 = u).
 template <class K>
-__global__ void __launch_bounds__(K::NS) k_adj_pred(const AdjPredP<K> p) {
+__global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
   using PDE = typename K::PDE;
+  using Plan = AdjPlan<K>;
   constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, NPAR = K::NPAR;
-  constexpr int PL = n * M * NS;                 // one space-time level
-  __shared__ double pred[NPAR > 0 ? NPAR * NS : 1];
-  const int a = threadIdx.x;
-  double* QI = p.scratch + (int64_t)blockIdx.x * p.slot_doubles;   // [R+1][n][M][NS]
-  double* FS = QI + (int64_t)(p.R + 1) * PL;                         // [D][n][M][NS]
-  double* RB = FS + (int64_t)D * PL;                                 // [n][M][NS]
-  double* QB = RB + PL;                                              // [n][M][NS]
+  constexpr int CPB = K::CPB, S = Plan::S;
+  __shared__ __align__(16) double smem[CPB * Plan::CELL];
+  __shared__ double pred[NPAR > 0 ? CPB * NPAR * NS : 1];
+  const int lc = threadIdx.x / NS;
+  const int a = threadIdx.x - lc * NS;
+  double* A = smem + lc * Plan::CELL;          // published slices
+  double* B = A + S * Plan::SL;                // pencil results
+  double* slot = p.scratch + (int64_t)blockIdx.x * p.slot_doubles;
+  const int64_t LV = (int64_t)n * M * CPB * NS;
+  auto it_at = [&](int r, int t, int v) -> double& {
+    return slot[(r - 1) * LV + ((int64_t)(t * M + v) * CPB + lc) * NS + a];
+  };
   const double c = (*p.dt) * p.inv_h;
-  auto at = [](double* base, int tt, int v, int nd) -> double& { return base[(tt * M + v) * NS + nd]; };
 
-  for (int64_t cell = blockIdx.x; cell < p.ncells; cell += gridDim.x) {
+  for (int64_t c0 = (int64_t)blockIdx.x * CPB; c0 < p.ncells; c0 += (int64_t)gridDim.x * CPB) {
+    const int64_t cell = c0 + lc;
+    const bool live = cell < p.ncells;
+    const int64_t cs = live ? cell : 0;
     double u[M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) u[v] = p.Q[(cell * NS + a) * M + v];
-    const auto cp = PDE::template cell<double>(p.par + cell * NPAR);
+    for (int v = 0; v < M; ++v) u[v] = p.Q[(cs * NS + a) * M + v];
+    const auto cp = PDE::template cell<double>(p.par + cs * NPAR);
     double pb[NPAR > 0 ? NPAR : 1];
 #pragma unroll
     for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
 
-    // ---- recompute the Picard iterates (full iterations) ----
-    for (int tt = 0; tt < n; ++tt)
+    // Forward pencils: B <- sum_i D_i F_i(A) on ns slices.
+    auto fwd_contract = [&](auto NS_) {
+      constexpr int ns = decltype(NS_)::value;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        if (a < ns * NF) {
+          const int tt = a / NF, b = a - tt * NF;
+          double out[n][M];
 #pragma unroll
-      for (int v = 0; v < M; ++v) at(QI, tt, v, a) = u[v];
-    for (int r = 1; r <= p.R; ++r) {
-      const double* Qp = QI + (int64_t)(r - 1) * PL;
-      for (int tt = 0; tt < n; ++tt) {
-        double q[M];
+          for (int k = 0; k < n; ++k)
 #pragma unroll
-        for (int v = 0; v < M; ++v) q[v] = Qp[(tt * M + v) * NS + a];
-        static_for<0, D>([&](auto I_) {
-          constexpr int I = decltype(I_)::value;
-          double F[M];
-          PDE::template flux<I>(q, F, p.g, cp);
+            for (int v = 0; v < M; ++v) out[k][v] = 0.0;
 #pragma unroll
-          for (int v = 0; v < M; ++v) at(FS + I * PL, tt, v, a) = F[v];
-        });
-      }
-      __syncthreads();
-      for (int tt = 0; tt < n; ++tt) {
-        double rhs[M];
-#pragma unroll
-        for (int v = 0; v < M; ++v) rhs[v] = 0.0;
-        static_for<0, D>([&](auto I_) {
-          constexpr int I = decltype(I_)::value;
-          const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
           for (int j = 0; j < n; ++j) {
-            const int nd = pencil_node<n, I>(fb, j);
-            const double dj = p.t.D[ai][j];
+            const int nd = pencil_node<n, I>(b, j);
+            double qn[M], F[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) rhs[v] += dj * at(FS + I * PL, tt, v, nd);
+            for (int v = 0; v < M; ++v) qn[v] = A[K::lidx(tt, v, nd)];
+            PDE::template flux<I>(qn, F, p.g, cp);
+#pragma unroll
+            for (int k = 0; k < n; ++k)
+#pragma unroll
+              for (int v = 0; v < M; ++v) out[k][v] = fma(p.t.D[k][j], F[v], out[k][v]);
           }
-        });
 #pragma unroll
-        for (int v = 0; v < M; ++v) at(RB, tt, v, a) = rhs[v];
-      }
-      double* Qr = QI + (int64_t)r * PL;
-      for (int tt = 0; tt < n; ++tt)
+          for (int k = 0; k < n; ++k) {
+            const int nd = pencil_node<n, I>(b, k);
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-          double s = 0.0;
-          for (int l = 0; l < n; ++l) s += p.t.P[tt][l] * at(RB, l, v, a);
-          Qr[(tt * M + v) * NS + a] = u[v] - c * s;
+            for (int v = 0; v < M; ++v) {
+              if constexpr (I == 0) B[K::lidx(tt, v, nd)] = out[k][v];
+              else B[K::lidx(tt, v, nd)] += out[k][v];
+            }
+          }
         }
-      __syncthreads();
+        __syncthreads();
+      });
+    };
+    // Reverse pencils of axis I: B <- D_I^T A on ns slices.
+    auto rev_contract = [&](auto NS_, auto I_) {
+      constexpr int ns = decltype(NS_)::value, I = decltype(I_)::value;
+      if (a < ns * NF) {
+        const int tt = a / NF, b = a - tt * NF;
+        double in[n][M];
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const int nd = pencil_node<n, I>(b, j);
+#pragma unroll
+          for (int v = 0; v < M; ++v) in[j][v] = A[K::lidx(tt, v, nd)];
+        }
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const int nd = pencil_node<n, I>(b, k);
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < n; ++j) s = fma(p.t.D[j][k], in[j][v], s);
+            B[K::lidx(tt, v, nd)] = s;
+          }
+        }
+      }
+    };
+
+    // ---- 1. recompute the Picard iterates ----
+    double q[n][M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) A[K::lidx(0, v, a)] = u[v];
+    __syncthreads();
+    fwd_contract(std::integral_constant<int, 1>{});
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      const double rv = B[K::lidx(0, v, a)];
+#pragma unroll
+      for (int t = 0; t < n; ++t) q[t][v] = u[v] - c * (p.t.Ps[t] * rv);
+    }
+    for (int r = 2; r <= p.R; ++r) {
+#pragma unroll
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) it_at(r - 1, t, v) = q[t][v];
+      double acc[n][M];
+#pragma unroll
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) acc[t][v] = 0.0;
+      static_for<0, Plan::NB>([&](auto B_) {
+        constexpr int t0 = decltype(B_)::value * S;
+        constexpr int ns = (n - t0) < S ? (n - t0) : S;
+        __syncthreads();                       // previous readers of A and B are done
+#pragma unroll
+        for (int tt = 0; tt < ns; ++tt)
+#pragma unroll
+          for (int v = 0; v < M; ++v) A[K::lidx(tt, v, a)] = q[t0 + tt][v];
+        __syncthreads();
+        fwd_contract(std::integral_constant<int, ns>{});
+#pragma unroll
+        for (int tt = 0; tt < ns; ++tt)
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            const double rv = B[K::lidx(tt, v, a)];
+#pragma unroll
+            for (int t = 0; t < n; ++t) acc[t][v] = fma(p.t.P[t][t0 + tt], rv, acc[t][v]);
+          }
+      });
+#pragma unroll
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) q[t][v] = u[v] - c * acc[t][v];
     }
 
-    // ---- bars of qbar and Fbar_i at this node ----
-    const double* TB = p.tb + cell * K::TRACE_ELEMS;
-    const double* Gc = p.Qbar + cell * NS * M;
-    double qbb[M], Fbb[D][M];
-#pragma unroll
-    for (int v = 0; v < M; ++v) qbb[v] = 0.0;
-    static_for<0, D>([&](auto I_) {
-      constexpr int I = decltype(I_)::value;
-      const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
-      const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb * M;
-      const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb * M;
-#pragma unroll
-      for (int v = 0; v < M; ++v) {
-        qbb[v] += p.t.FL[ai] * tl[v] + p.t.FR[ai] * trr[v];
-        Fbb[I][v] = (K::NQ == 2) ? p.t.FL[ai] * tl[NF * M + v] + p.t.FR[ai] * trr[NF * M + v] : 0.0;
-      }
-      for (int k = 0; k < n; ++k) {
-        const int nd = pencil_node<n, I>(fb, k);
-        const double kv = c * p.t.Kv[k][ai];
-#pragma unroll
-        for (int v = 0; v < M; ++v) Fbb[I][v] += kv * Gc[nd * M + v];
-      }
-    });
+    // ---- 2. bars of qbar and Fbar_i at this node, then q^R bar ----
+    const double* TB = p.tb + cs * K::TRACE_ELEMS;
+    const double* Gc = p.Qbar + cs * NS * M;
+    double qb[n][M];
     {
-      const double* QR = QI + (int64_t)p.R * PL;
-      for (int tt = 0; tt < n; ++tt) {
-        double q[M], acc[M];
-        const double wt = p.t.w[tt];
+      double qbb[M], Fbb[D][M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) qbb[v] = 0.0;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
+        const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb * M;
+        const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb * M;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          q[v] = QR[(tt * M + v) * NS + a];
-          acc[v] = wt * qbb[v];
+          qbb[v] += p.t.FL[ai] * tl[v] + p.t.FR[ai] * trr[v];
+          Fbb[I][v] = (K::NQ == 2) ? p.t.FL[ai] * tl[NF * M + v] + p.t.FR[ai] * trr[NF * M + v] : 0.0;
         }
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const int nd = pencil_node<n, I>(fb, k);
+          const double kv = c * p.t.Kv[k][ai];
+#pragma unroll
+          for (int v = 0; v < M; ++v) Fbb[I][v] += kv * Gc[nd * M + v];
+        }
+      });
+#pragma unroll
+      for (int t = 0; t < n; ++t) {
+        const double wt = p.t.w[t];
+#pragma unroll
+        for (int v = 0; v < M; ++v) qb[t][v] = wt * qbb[v];
         static_for<0, D>([&](auto I_) {
           constexpr int I = decltype(I_)::value;
           double fw[M];
 #pragma unroll
           for (int v = 0; v < M; ++v) fw[v] = wt * Fbb[I][v];
-          PDE::template flux_adj<I>(q, fw, acc, pb, p.g, cp);
+          PDE::template flux_adj<I>(q[t], fw, qb[t], pb, p.g, cp);
         });
-#pragma unroll
-        for (int v = 0; v < M; ++v) at(QB, tt, v, a) = acc[v];
       }
     }
-
-    // ---- reverse sweep over the Picard iterations ----
     double ub[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) ub[v] = Gc[a * M + v];
-    for (int r = p.R; r >= 1; --r) {
+
+    // ---- 3. reverse sweep over the Picard iterations ----
+    for (int r = p.R; r >= 2; --r) {
+      double rb[n][M], nb[n][M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+#pragma unroll
+        for (int t = 0; t < n; ++t) ub[v] += qb[t][v];
+#pragma unroll
+        for (int l = 0; l < n; ++l) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < n; ++t) s = fma(p.t.P[t][l], qb[t][v], s);
+          rb[l][v] = -c * s;
+        }
+      }
+#pragma unroll
       for (int l = 0; l < n; ++l)
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-          double s = 0.0;
-          for (int tt = 0; tt < n; ++tt) s += p.t.P[tt][l] * at(QB, tt, v, a);
-          at(RB, l, v, a) = -c * s;
-        }
+        for (int v = 0; v < M; ++v) nb[l][v] = 0.0;
+      static_for<0, Plan::NB>([&](auto B_) {
+        constexpr int l0 = decltype(B_)::value * S;
+        constexpr int ns = (n - l0) < S ? (n - l0) : S;
+        double qp[ns][M];
 #pragma unroll
-      for (int v = 0; v < M; ++v)
-        for (int tt = 0; tt < n; ++tt) ub[v] += at(QB, tt, v, a);
-      __syncthreads();
-      const double* Qp = QI + (int64_t)(r - 1) * PL;
-      for (int tt = 0; tt < n; ++tt) {
-        double q[M], nb[M];
+        for (int tt = 0; tt < ns; ++tt)
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-          q[v] = Qp[(tt * M + v) * NS + a];
-          nb[v] = 0.0;
-        }
+          for (int v = 0; v < M; ++v) qp[tt][v] = it_at(r - 1, l0 + tt, v);
+        __syncthreads();                       // previous readers of A and B are done
+#pragma unroll
+        for (int tt = 0; tt < ns; ++tt)
+#pragma unroll
+          for (int v = 0; v < M; ++v) A[K::lidx(tt, v, a)] = rb[l0 + tt][v];
+        __syncthreads();
         static_for<0, D>([&](auto I_) {
           constexpr int I = decltype(I_)::value;
-          const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
-          double Fi[M];
+          if constexpr (I > 0) __syncthreads();   // B read by every node below
+          rev_contract(std::integral_constant<int, ns>{}, I_);
+          __syncthreads();
 #pragma unroll
-          for (int v = 0; v < M; ++v) Fi[v] = 0.0;
-          for (int k = 0; k < n; ++k) {
-            const int nd = pencil_node<n, I>(fb, k);
-            const double dk = p.t.D[k][ai];
+          for (int tt = 0; tt < ns; ++tt) {
+            double fb[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) Fi[v] += dk * at(RB, tt, v, nd);
+            for (int v = 0; v < M; ++v) fb[v] = B[K::lidx(tt, v, a)];
+            PDE::template flux_adj<I>(qp[tt], fb, nb[l0 + tt], pb, p.g, cp);
           }
-          PDE::template flux_adj<I>(q, Fi, nb, pb, p.g, cp);
         });
+      });
 #pragma unroll
-        for (int v = 0; v < M; ++v) at(QB, tt, v, a) = nb[v];
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) qb[t][v] = nb[t][v];
+    }
+    // r = 1: q^1 = u - (dt/h) Ps rhs(u), one slice
+    {
+      double rb0[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < n; ++t) {
+          ub[v] += qb[t][v];
+          s = fma(p.t.Ps[t], qb[t][v], s);
+        }
+        rb0[v] = -c * s;
       }
       __syncthreads();
+#pragma unroll
+      for (int v = 0; v < M; ++v) A[K::lidx(0, v, a)] = rb0[v];
+      __syncthreads();
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        if constexpr (I > 0) __syncthreads();
+        rev_contract(std::integral_constant<int, 1>{}, I_);
+        __syncthreads();
+        double fb[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) fb[v] = B[K::lidx(0, v, a)];
+        PDE::template flux_adj<I>(u, fb, ub, pb, p.g, cp);
+      });
     }
-#pragma unroll
-    for (int v = 0; v < M; ++v)
-      for (int tt = 0; tt < n; ++tt) ub[v] += at(QB, tt, v, a);
     __syncthreads();                       // every read of this cell's G is done
+    if (live) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) p.Qbar[(cell * NS + a) * M + v] = ub[v];
+      for (int v = 0; v < M; ++v) p.Qbar[(cell * NS + a) * M + v] = ub[v];
+    }
     if constexpr (NPAR > 0) {
 #pragma unroll
-      for (int k = 0; k < NPAR; ++k) pred[k * NS + a] = pb[k];
+      for (int k = 0; k < NPAR; ++k) pred[(lc * NPAR + k) * NS + a] = pb[k];
       __syncthreads();
-      if (a < NPAR && p.pbar) {
+      if (a < NPAR && live && p.pbar) {
         double acc = 0.0;
-        for (int j = 0; j < NS; ++j) acc += pred[a * NS + j];
+        for (int j = 0; j < NS; ++j) acc += pred[(lc * NPAR + a) * NS + j];
         p.pbar[cell * NPAR + a] += acc;
       }
-      __syncthreads();
     }
+    __syncthreads();                       // LDS and pred reused by the next cell
   }
 }
 
@@ -406,8 +538,22 @@ int launch_adjoint(const LaunchArgs& a) {
   pp.R = a.R;
   for (int k = 0; k < 4; ++k) pp.g.c[k] = a.gp[k];
   pp.t = make_ktab<K::n, double>(*a.tab);
-  int64_t G = a.adj_nslots < a.ncells ? a.adj_nslots : a.ncells;
-  hipLaunchKernelGGL(k_adj_pred<K>, dim3((unsigned)G), dim3(K::NS), 0, a.stream, pp);
+  // Persistent blocks: no more than fit on the device at once, so every
+  // block starts together and walks the same number of cells.
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_pred<K>, K::THREADS, 0);
+    if (e != hipSuccess) return (int)e;
+    resident = cus * (per_cu > 0 ? per_cu : 1);
+  }
+  int64_t G = (a.ncells + K::CPB - 1) / K::CPB;
+  if (G > a.adj_nslots) G = a.adj_nslots;
+  if (G > resident) G = resident;
+  hipLaunchKernelGGL(k_adj_pred<K>, dim3((unsigned)G), dim3(K::THREADS), 0, a.stream, pp);
   return (int)hipGetLastError();
 }
 

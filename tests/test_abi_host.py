@@ -115,3 +115,27 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+@pytest.mark.parametrize("name", ["C4", "C5"])
+def test_query_adjoint_workspace(L, name):
+    """The adjoint adds a copy of Q, the hull's bars and per-block slots that
+    hold the Picard iterates q^1..q^{R-1} of one block's cells (at most 2048
+    blocks and 2 GiB)."""
+    wl = inputs.preset(name)
+    _, _, w = _lib.query(cfg_of(wl))
+    c = cfg_of(wl)
+    c.adjoint = 1
+    _, _, wa = _lib.query(c)
+    n, d, m = wl.n, wl.dim, wl.m
+    ns = n ** d
+    R = wl.picard_iters or wl.order + 1
+    cpb = 1 if ns >= 128 else 128 // ns
+    slot = max(R - 1, 1) * n * m * ns * cpb * 8
+    nslots = min(wl.ncells, 2048, (2 << 30) // slot)
+    nq = 2 if wl.pde == inputs.EULER else 1
+    extra = wl.ncells * m * ns * 8 + wl.ncells * 2 * d * nq * m * n ** (d - 1) * 8 + nslots * slot
+    assert extra <= wa - w <= extra + 3 * 256
+    assert nslots * slot <= 2 << 30
+    c.precision = inputs.FP32
+    assert L.adg_query(ctypes.byref(c), None, None, None) in (_lib.ADG_OK, _lib.ADG_ERR_UNSUPPORTED)
