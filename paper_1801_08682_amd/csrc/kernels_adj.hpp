@@ -33,127 +33,133 @@ struct AdjCorrP {
   double* pbar;          // per-cell material bars (nullable)
   int64_t ncells;
   int nc[3];
+  int brick[3];
   double inv_h;
   Gconst<double> g;
   double LL[K::n], LR[K::n];
 };
 
+// Same schedule as the forward corrector: CCPB cells per workgroup, one
+// thread per (face, face node) task, cells taken in the XCD-aware brick walk
+// so the neighbours' G and traces are shared in L2.
 template <class K>
-__global__ void __launch_bounds__(K::CT) k_adj_corr(const AdjCorrP<K> p) {
+__global__ void __launch_bounds__(K::CTHREADS) k_adj_corr(const AdjCorrP<K> p) {
   using PDE = typename K::PDE;
   constexpr int n = K::n, M = K::M, NF = K::NF, D = K::D, CT = K::CT, NPAR = K::NPAR;
-  constexpr int FT = 2 * D * NF;
-  __shared__ double lamL[FT], lamR[FT], sbp[FT];
-  __shared__ double smax[2 * D], sbar[2 * D];
-  __shared__ int bstar[2 * D], sstar[2 * D];
-  __shared__ double pred[NPAR > 0 ? NPAR * CT : 1];
-  const int t = threadIdx.x;
+  constexpr int FT = 2 * D * NF, CC = K::CCPB;
+  __shared__ double lamL[CC][FT], lamR[CC][FT], sbp[CC][FT];
+  __shared__ double smax[CC][2 * D], sbar[CC][2 * D];
+  __shared__ int bstar[CC][2 * D], sstar[CC][2 * D];
+  __shared__ double pred[NPAR > 0 ? CC * NPAR * CT : 1];
+  const int lc = threadIdx.x / CT;
+  const int t = threadIdx.x - lc * CT;
   const double cdt = (*p.dt) * p.inv_h;
+  const int64_t groups = (p.ncells + CC - 1) / CC;
+  const int64_t grp = xcd_group(groups);
+  if (grp >= groups) return;                    // whole workgroup leaves together
+  const int64_t gc = grp * CC + lc;
+  const bool live = gc < p.ncells;
+  const int64_t cell = live ? brick_cell(gc, p.nc, p.brick) : 0;
 
-  for (GroupIter it(p.ncells); it.g < it.end; it.g += it.step) {
-    const int64_t cell = it.g;
-    double pb[NPAR > 0 ? NPAR : 1];
+  double pb[NPAR > 0 ? NPAR : 1];
 #pragma unroll
-    for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
-    double qL[M], qR[M], Fb[M], dq[M];
-    int f = 0, b = 0, i = 0, s = 0;
-    int64_t cL = 0, cR = 0;
-    const bool ftask = t < FT;
-    if (ftask) {
-      f = t / NF;
-      b = t - f * NF;
-      i = f >> 1;
-      s = f & 1;
-      cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
-      cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
-      const double* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b * M;
-      const double* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b * M;
+  for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
+  double qL[M], qR[M], Fb[M], dq[M];
+  int f = 0, b = 0, i = 0, s = 0;
+  const bool ftask = live && t < FT;
+  if (ftask) {
+    f = t / NF;
+    b = t - f * NF;
+    i = f >> 1;
+    s = f & 1;
+    const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
+    const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
+    const double* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b * M;
+    const double* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b * M;
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-        qL[v] = trL[v];
-        qR[v] = trR[v];
-        dq[v] = qR[v] - qL[v];
-        Fb[v] = 0.0;
-      }
-      const auto pL = PDE::template cell<double>(p.par + cL * NPAR);
-      const auto pR = PDE::template cell<double>(p.par + cR * NPAR);
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        if (i == I) {
-          lamL[t] = PDE::template speed<I>(qL, p.g, pL);
-          lamR[t] = PDE::template speed<I>(qR, p.g, pR);
-          // Fb* = -(dt/h) (LR^T G_L)_b + (dt/h) (LL^T G_R)_b
-          const double* GL = p.G + cL * K::NS * M;
-          const double* GR = p.G + cR * K::NS * M;
+    for (int v = 0; v < M; ++v) {
+      qL[v] = trL[v];
+      qR[v] = trR[v];
+      dq[v] = qR[v] - qL[v];
+      Fb[v] = 0.0;
+    }
+    const auto pL = PDE::template cell<double>(p.par + cL * NPAR);
+    const auto pR = PDE::template cell<double>(p.par + cR * NPAR);
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      if (i == I) {
+        lamL[lc][t] = PDE::template speed<I>(qL, p.g, pL);
+        lamR[lc][t] = PDE::template speed<I>(qR, p.g, pR);
+        // Fb* = -(dt/h) (LR^T G_L)_b + (dt/h) (LL^T G_R)_b
+        const double* GL = p.G + cL * K::NS * M;
+        const double* GR = p.G + cR * K::NS * M;
 #pragma unroll
-          for (int k = 0; k < n; ++k) {
-            const int nd = pencil_node<n, I>(b, k);
+        for (int k = 0; k < n; ++k) {
+          const int nd = pencil_node<n, I>(b, k);
 #pragma unroll
-            for (int v = 0; v < M; ++v)
-              Fb[v] += -cdt * p.LR[k] * GL[nd * M + v] + cdt * p.LL[k] * GR[nd * M + v];
-          }
+          for (int v = 0; v < M; ++v)
+            Fb[v] += -cdt * p.LR[k] * GL[nd * M + v] + cdt * p.LL[k] * GR[nd * M + v];
         }
-      });
-      double sp = 0.0;
+      }
+    });
+    double sp = 0.0;
 #pragma unroll
-      for (int v = 0; v < M; ++v) sp += Fb[v] * dq[v];
-      sbp[t] = -0.5 * sp;
+    for (int v = 0; v < M; ++v) sp += Fb[v] * dq[v];
+    sbp[lc][t] = -0.5 * sp;
+  }
+  __syncthreads();
+  if (live && t < 2 * D) {
+    double best = -1.0, acc = 0.0;
+    int bs = 0, ss = 0;
+    for (int bb = 0; bb < NF; ++bb) {
+      const double l0 = lamL[lc][t * NF + bb], l1 = lamR[lc][t * NF + bb];
+      if (l0 > best) { best = l0; bs = bb; ss = 0; }
+      if (l1 > best) { best = l1; bs = bb; ss = 1; }
+      acc += sbp[lc][t * NF + bb];
     }
+    smax[lc][t] = best;
+    bstar[lc][t] = bs;
+    sstar[lc][t] = ss;
+    sbar[lc][t] = acc;
+  }
+  __syncthreads();
+  if (ftask) {
+    // this cell is the left state of its right face (s = 1) and the right
+    // state of its left face (s = 0)
+    double tq[M], tf[M], own[M];
+    const double sgn = s ? 0.5 : -0.5;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      own[v] = s ? qL[v] : qR[v];
+      tq[v] = sgn * smax[lc][f] * Fb[v];
+      tf[v] = 0.5 * Fb[v];
+    }
+    const auto pc = PDE::template cell<double>(p.par + cell * NPAR);
+    const bool mine = (bstar[lc][f] == b) && (sstar[lc][f] == (s ? 0 : 1));
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      if (i == I) {
+        if (mine) PDE::template speed_adj<I>(own, sbar[lc][f], tq, pb, p.g, pc);
+        if constexpr (K::NQ == 1) PDE::template flux_adj<I>(own, tf, tq, pb, p.g, pc);
+      }
+    });
+    double* out = p.tb + cell * K::TRACE_ELEMS + (int64_t)f * K::NQ * NF * M + b * M;
+#pragma unroll
+    for (int v = 0; v < M; ++v) out[v] = tq[v];
+    if constexpr (K::NQ == 2) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) out[NF * M + v] = tf[v];
+    }
+  }
+  if constexpr (NPAR > 0) {
+#pragma unroll
+    for (int k = 0; k < NPAR; ++k) pred[(lc * NPAR + k) * CT + t] = pb[k];
     __syncthreads();
-    if (t < 2 * D) {
-      double best = -1.0, acc = 0.0;
-      int bs = 0, ss = 0;
-      for (int bb = 0; bb < NF; ++bb) {
-        const double l0 = lamL[t * NF + bb], l1 = lamR[t * NF + bb];
-        if (l0 > best) { best = l0; bs = bb; ss = 0; }
-        if (l1 > best) { best = l1; bs = bb; ss = 1; }
-        acc += sbp[t * NF + bb];
-      }
-      smax[t] = best;
-      bstar[t] = bs;
-      sstar[t] = ss;
-      sbar[t] = acc;
+    if (live && t < NPAR && p.pbar) {
+      double acc = 0.0;
+      for (int j = 0; j < CT; ++j) acc += pred[(lc * NPAR + t) * CT + j];
+      p.pbar[cell * NPAR + t] += acc;
     }
-    __syncthreads();
-    if (ftask) {
-      // this cell is the left state of its right face (s = 1) and the right
-      // state of its left face (s = 0)
-      double tq[M], tf[M];
-      const double* own = s ? qL : qR;
-      const double sgn = s ? 0.5 : -0.5;
-#pragma unroll
-      for (int v = 0; v < M; ++v) {
-        tq[v] = sgn * smax[f] * Fb[v];
-        tf[v] = 0.5 * Fb[v];
-      }
-      const auto pc = PDE::template cell<double>(p.par + cell * NPAR);
-      const bool mine = (bstar[f] == b) && (sstar[f] == (s ? 0 : 1));
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        if (i == I) {
-          if (mine) PDE::template speed_adj<I>(own, sbar[f], tq, pb, p.g, pc);
-          if constexpr (K::NQ == 1) PDE::template flux_adj<I>(own, tf, tq, pb, p.g, pc);
-        }
-      });
-      double* out = p.tb + cell * K::TRACE_ELEMS + (int64_t)f * K::NQ * NF * M + b * M;
-#pragma unroll
-      for (int v = 0; v < M; ++v) out[v] = tq[v];
-      if constexpr (K::NQ == 2) {
-#pragma unroll
-        for (int v = 0; v < M; ++v) out[NF * M + v] = tf[v];
-      }
-    }
-    if constexpr (NPAR > 0) {
-#pragma unroll
-      for (int k = 0; k < NPAR; ++k) pred[k * CT + t] = pb[k];
-      __syncthreads();
-      if (t < NPAR && p.pbar) {
-        double acc = 0.0;
-        for (int j = 0; j < CT; ++j) acc += pred[t * CT + j];
-        p.pbar[cell * NPAR + t] += acc;
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -519,8 +525,10 @@ int launch_adjoint(const LaunchArgs& a) {
     pc.LL[k] = a.tab->LL[k];
     pc.LR[k] = a.tab->LR[k];
   }
-  const int64_t Gc = reduce_grid<K>(a.ncells);
-  hipLaunchKernelGGL(k_adj_corr<K>, dim3((unsigned)Gc), dim3(K::CT), 0, a.stream, pc);
+  for (int k = 0; k < 3; ++k) pc.brick[k] = a.brick[k];
+  const int64_t groups = (a.ncells + K::CCPB - 1) / K::CCPB;
+  const int64_t Gc = 8 * ((groups + 7) / 8);
+  hipLaunchKernelGGL(k_adj_corr<K>, dim3((unsigned)Gc), dim3(K::CTHREADS), 0, a.stream, pc);
   e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
 

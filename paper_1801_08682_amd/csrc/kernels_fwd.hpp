@@ -390,27 +390,6 @@ __device__ __forceinline__ double block_max(double x, double* red) {
   return r;
 }
 
-// Cell-group schedule of the reduction kernels: XCD-aware when the grid is a
-// multiple of 8 (workgroup k runs on XCD k mod 8; each XCD walks one
-// contiguous range of cells so neighbour traces are shared in its L2).
-struct GroupIter {
-  int64_t g, end, step;
-  __device__ GroupIter(int64_t groups) {
-    const int64_t G = gridDim.x;
-    if (G % 8 == 0) {
-      const int64_t x = blockIdx.x % 8, k = blockIdx.x / 8, per = G / 8;
-      const int64_t span = (groups + 7) / 8;
-      g = x * span + k;
-      end = min(groups, (x + 1) * span);
-      step = per;
-    } else {
-      g = blockIdx.x;
-      end = groups;
-      step = G;
-    }
-  }
-};
-
 template <class K>
 struct CorrP {
   double* Q;
