@@ -250,6 +250,7 @@ adg_status adg_init(const adg_config* cfg, void* d_workspace, int64_t workspace_
     const double g = cfg->pde_param[0] == 0.0 ? 1.4 : cfg->pde_param[0];
     c->gp[0] = g;
     c->gp[1] = g - 1.0;
+    c->gp[2] = g / (g - 1.0);
   } else {
     for (int k = 0; k < 4; ++k) c->gp[k] = cfg->pde_param[k];
   }

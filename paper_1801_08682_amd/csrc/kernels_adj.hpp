@@ -203,6 +203,12 @@ constexpr int64_t adj_slot_doubles(int R) {
   return levels * K::n * K::M * K::NS * K::CPB;
 }
 
+// LDS index in a buffer of S time slices (the forward predictor's layout).
+template <class K, int S>
+__device__ __forceinline__ int alidx(int tt, int v, int pos) {
+  return K::template lidx_e<S>(tt * K::NSP + pos, v);
+}
+
 // One thread per spatial node, CPB cells per workgroup, one cell per thread
 // group at a time (persistent blocks, each with its scratch slot).  The
 // node thread keeps time columns in registers; spatial contractions go
@@ -261,22 +267,25 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
             const int nd = pencil_node<n, I>(b, j);
             double qn[M], F[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) qn[v] = A[K::lidx(tt, v, nd)];
+            for (int v = 0; v < M; ++v) qn[v] = A[alidx<K, S>(tt, v, nd)];
             PDE::template flux<I>(qn, F, p.g, cp);
 #pragma unroll
             for (int k = 0; k < n; ++k)
 #pragma unroll
               for (int v = 0; v < M; ++v) out[k][v] = fma(p.t.D[k][j], F[v], out[k][v]);
           }
+          // every read of the pencil before any write: no serialised
+          // read-modify-write through possibly aliasing stores
+          if constexpr (I > 0) {
 #pragma unroll
-          for (int k = 0; k < n; ++k) {
-            const int nd = pencil_node<n, I>(b, k);
+            for (int k = 0; k < n; ++k)
 #pragma unroll
-            for (int v = 0; v < M; ++v) {
-              if constexpr (I == 0) B[K::lidx(tt, v, nd)] = out[k][v];
-              else B[K::lidx(tt, v, nd)] += out[k][v];
-            }
+              for (int v = 0; v < M; ++v) out[k][v] += B[alidx<K, S>(tt, v, pencil_node<n, I>(b, k))];
           }
+#pragma unroll
+          for (int k = 0; k < n; ++k)
+#pragma unroll
+            for (int v = 0; v < M; ++v) B[alidx<K, S>(tt, v, pencil_node<n, I>(b, k))] = out[k][v];
         }
         __syncthreads();
       });
@@ -291,7 +300,7 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
         for (int j = 0; j < n; ++j) {
           const int nd = pencil_node<n, I>(b, j);
 #pragma unroll
-          for (int v = 0; v < M; ++v) in[j][v] = A[K::lidx(tt, v, nd)];
+          for (int v = 0; v < M; ++v) in[j][v] = A[alidx<K, S>(tt, v, nd)];
         }
 #pragma unroll
         for (int k = 0; k < n; ++k) {
@@ -301,7 +310,7 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
             double s = 0.0;
 #pragma unroll
             for (int j = 0; j < n; ++j) s = fma(p.t.D[j][k], in[j][v], s);
-            B[K::lidx(tt, v, nd)] = s;
+            B[alidx<K, S>(tt, v, nd)] = s;
           }
         }
       }
@@ -310,12 +319,12 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
     // ---- 1. recompute the Picard iterates ----
     double q[n][M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) A[K::lidx(0, v, a)] = u[v];
+    for (int v = 0; v < M; ++v) A[alidx<K, S>(0, v, a)] = u[v];
     __syncthreads();
     fwd_contract(std::integral_constant<int, 1>{});
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      const double rv = B[K::lidx(0, v, a)];
+      const double rv = B[alidx<K, S>(0, v, a)];
 #pragma unroll
       for (int t = 0; t < n; ++t) q[t][v] = u[v] - c * (p.t.Ps[t] * rv);
     }
@@ -336,14 +345,14 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
 #pragma unroll
         for (int tt = 0; tt < ns; ++tt)
 #pragma unroll
-          for (int v = 0; v < M; ++v) A[K::lidx(tt, v, a)] = q[t0 + tt][v];
+          for (int v = 0; v < M; ++v) A[alidx<K, S>(tt, v, a)] = q[t0 + tt][v];
         __syncthreads();
         fwd_contract(std::integral_constant<int, ns>{});
 #pragma unroll
         for (int tt = 0; tt < ns; ++tt)
 #pragma unroll
           for (int v = 0; v < M; ++v) {
-            const double rv = B[K::lidx(tt, v, a)];
+            const double rv = B[alidx<K, S>(tt, v, a)];
 #pragma unroll
             for (int t = 0; t < n; ++t) acc[t][v] = fma(p.t.P[t][t0 + tt], rv, acc[t][v]);
           }
@@ -429,7 +438,7 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
 #pragma unroll
         for (int tt = 0; tt < ns; ++tt)
 #pragma unroll
-          for (int v = 0; v < M; ++v) A[K::lidx(tt, v, a)] = rb[l0 + tt][v];
+          for (int v = 0; v < M; ++v) A[alidx<K, S>(tt, v, a)] = rb[l0 + tt][v];
         __syncthreads();
         static_for<0, D>([&](auto I_) {
           constexpr int I = decltype(I_)::value;
@@ -440,7 +449,7 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
           for (int tt = 0; tt < ns; ++tt) {
             double fb[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) fb[v] = B[K::lidx(tt, v, a)];
+            for (int v = 0; v < M; ++v) fb[v] = B[alidx<K, S>(tt, v, a)];
             PDE::template flux_adj<I>(qp[tt], fb, nb[l0 + tt], pb, p.g, cp);
           }
         });
@@ -465,7 +474,7 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
       }
       __syncthreads();
 #pragma unroll
-      for (int v = 0; v < M; ++v) A[K::lidx(0, v, a)] = rb0[v];
+      for (int v = 0; v < M; ++v) A[alidx<K, S>(0, v, a)] = rb0[v];
       __syncthreads();
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
@@ -474,7 +483,7 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
         __syncthreads();
         double fb[M];
 #pragma unroll
-        for (int v = 0; v < M; ++v) fb[v] = B[K::lidx(0, v, a)];
+        for (int v = 0; v < M; ++v) fb[v] = B[alidx<K, S>(0, v, a)];
         PDE::template flux_adj<I>(u, fb, ub, pb, p.g, cp);
       });
     }

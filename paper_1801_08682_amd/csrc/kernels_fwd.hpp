@@ -34,18 +34,31 @@ struct Fwd {
   // predictor block
   static constexpr int CPB = (NS >= 128) ? 1 : 128 / NS;
   static constexpr int THREADS = CPB * NS;
-  // LDS slice layout.  float64: node-major [slice][node][var] with the
-  // variables padded to an even count, so a node's values move as 16-byte
-  // words.  float: var-major planes [slice][var][node] whose stride is padded
-  // by 3 to shift consecutive planes across the LDS banks.  (Measured on the
-  // 3D Euler N = 4 predictor; the other choice is 4% slower in each case.)
-  static constexpr bool NODE_MAJOR = std::is_same<Real, double>::value;
-  static constexpr int NSP = NS + (NODE_MAJOR ? 0 : 3);
-  static constexpr int MP = NODE_MAJOR ? (M + 1) / 2 * 2 : M;
-  __device__ static __forceinline__ int lidx(int tt, int v, int pos) {
-    if constexpr (NODE_MAJOR) return (tt * NSP + pos) * MP + v;
-    else return (tt * M + v) * NSP + pos;
+  // LDS slice layout, as planes indexed by the slot e = tt * NSP + node of a
+  // buffer of NSL time slices.  float64: the variable pairs (v, v+1) in
+  // 16-byte planes [pair][slice][node] and an odd last variable in an 8-byte
+  // plane, so a node's values move as 16-byte words plus at most one 8-byte
+  // word.  float: one plane per variable [var][slice][node], stride padded
+  // by 3.  The pencil tasks are dealt to the lanes in the order of
+  // TaskOrder below, which keeps every access free of bank conflicts.
+  static constexpr bool PAIRS = std::is_same<Real, double>::value;
+  static constexpr int NSP = NS + (PAIRS ? 0 : 3);
+  static constexpr int MP = M;
+  template <int NSL>
+  __device__ static __forceinline__ int lidx_e(int e, int v) {
+    if constexpr (PAIRS) {
+      constexpr int NP2 = M / 2;
+      if (v < 2 * NP2) return ((v >> 1) * NSL * NSP + e) * 2 + (v & 1);
+      return 2 * NP2 * NSL * NSP + e;
+    } else {
+      return v * NSL * NSP + e;
+    }
   }
+  __device__ static __forceinline__ int lidx(int tt, int v, int pos);
+  // Lanes the LDS serves per cycle for this layout's accesses: 16-byte words
+  // 16 lanes, 8-byte words 32 lanes, 4-byte words 64 lanes (64 banks of 4 B).
+  static constexpr int NGROUP = PAIRS ? 2 : 1;
+  static constexpr int group(int c) { return PAIRS ? (c == 0 ? 16 : 32) : 64; }
   static constexpr int LDS_BUDGET = 80 * 1024;
   static constexpr int SLICE_BYTES = 2 * NSP * MP * (int)sizeof(Real);
   static constexpr int pick_S() {
@@ -73,6 +86,64 @@ struct Fwd {
   static constexpr int CTHREADS = CCPB * CT;
   static constexpr int CORR_CELL_BYTES = (2 * D * NF * (M + 1) + 2 * D) * 8;
 };
+
+template <int D_, int N_, template <int> class PDET, class Real_>
+__device__ __forceinline__ int Fwd<D_, N_, PDET, Real_>::lidx(int tt, int v, int pos) {
+  return lidx_e<S>(tt * NSP + pos, v);
+}
+
+// Lane order of the pencil tasks of one axis for a batch of ns time slices.
+// Task (tt, b) is the pencil along axis I through face node b at slice tt; a
+// lane reads and writes the slots e0 + j n^I, j = 0..n-1, with e0 its first
+// node.  Greedy order: each lane takes the first unused task whose e0 is
+// distinct, modulo G, from the e0 of the lanes before it in its aligned
+// group of G lanes, for every G the layout's accesses are served in (fewer
+// constraints when none fits).  The offsets j n^I are the same on every
+// lane, so one order serves the whole pencil.
+template <int T>
+struct TaskOrder {
+  unsigned short e0[T];
+};
+
+template <class K, int ns, int I>
+constexpr TaskOrder<ns * K::NF> make_task_order() {
+  constexpr int n = K::n, NF = K::NF, T = ns * NF, s = ipow(n, I);
+  TaskOrder<T> r{};
+  int off[T] = {};
+  bool used[T] = {};
+  for (int task = 0; task < T; ++task) {
+    const int tt = task / NF, b = task % NF;
+    off[task] = tt * K::NSP + (b % s) + s * n * (b / s);
+  }
+  unsigned long long mask[2] = {0ull, 0ull};
+  for (int lane = 0; lane < T; ++lane) {
+    for (int c = 0; c < K::NGROUP; ++c)
+      if (lane % K::group(c) == 0) mask[c] = 0ull;
+    int pick = -1;
+    for (int keep = K::NGROUP; keep >= 0 && pick < 0; --keep) {
+      for (int k = 0; k < T && pick < 0; ++k) {
+        if (used[k]) continue;
+        bool ok = true;
+        for (int c = 0; c < keep; ++c)
+          if ((mask[c] >> (off[k] % K::group(c))) & 1ull) ok = false;
+        if (ok) pick = k;
+      }
+    }
+    used[pick] = true;
+    for (int c = 0; c < K::NGROUP; ++c) mask[c] |= 1ull << (off[pick] % K::group(c));
+    r.e0[lane] = (unsigned short)off[pick];
+  }
+  return r;
+}
+
+template <class K, int ns, int I>
+__constant__ TaskOrder<ns * K::NF> task_order = make_task_order<K, ns, I>();
+
+// First slot of this lane's pencil task (0 for lanes without a task).
+template <class K, int ns, int I>
+__device__ __forceinline__ int task_e0(int a) {
+  return a < ns * K::NF ? (int)task_order<K, ns, I>.e0[a] : 0;
+}
 
 template <class K>
 struct PredP {
@@ -117,14 +188,33 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
 #pragma unroll
     for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v];
   const int pa = a;
+  // First slot of this lane's pencil task for each batch size used and axis.
+  constexpr int TAIL = n - (K::NB - 1) * S;
+  int ordF[D], ordS[D], ordT[D];
+  static_for<0, D>([&](auto I_) {
+    constexpr int I = decltype(I_)::value;
+    ordF[I] = task_e0<K, 1, I>(a);
+    ordS[I] = task_e0<K, S, I>(a);
+    ordT[I] = (TAIL != S && TAIL != 1) ? task_e0<K, TAIL, I>(a) : 0;
+  });
+  auto e0_of = [&](auto NS_, auto I_) -> int {
+    constexpr int ns = decltype(NS_)::value, I = decltype(I_)::value;
+    if constexpr (ns == 1) return ordF[I];
+    else if constexpr (ns == S) return ordS[I];
+    else return ordT[I];
+  };
 
-  // Node role: publish time slices [t0, t0 + ns) of this node's column.
+  // Node role: publish time slices [t0, t0 + ns) of this node's column in
+  // the PDE's publish form.
   auto publish = [&](auto T0_, auto NS_) {
     constexpr int t0 = decltype(T0_)::value, ns = decltype(NS_)::value;
 #pragma unroll
-    for (int tt = 0; tt < ns; ++tt)
+    for (int tt = 0; tt < ns; ++tt) {
+      Real w[M];
+      PDE::pub(q[t0 + tt], w, p.g);
 #pragma unroll
-      for (int v = 0; v < M; ++v) Qs[K::lidx(tt, v, pa)] = q[t0 + tt][v];
+      for (int v = 0; v < M; ++v) Qs[K::lidx(tt, v, pa)] = w[v];
+    }
   };
   // Pencil role: for every published slice and axis I, evaluate F_I along a
   // pencil and contract with D; the three axis results are summed in Rs.
@@ -132,7 +222,8 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
     constexpr int ns = decltype(NS_)::value;
     static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
-      auto pencil = [&](int tt, int b) {
+      constexpr int sI = ipow(n, I);
+      auto pencil = [&](int e0) {
         Real out[n][M];
 #pragma unroll
         for (int k = 0; k < n; ++k)
@@ -140,31 +231,30 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
           for (int v = 0; v < M; ++v) out[k][v] = Real(0);
 #pragma unroll
         for (int j = 0; j < n; ++j) {
-          const int nd = pencil_node<n, I>(b, j);
+          const int e = e0 + j * sI;
           Real qn[M], F[M];
 #pragma unroll
-          for (int v = 0; v < M; ++v) qn[v] = Qs[K::lidx(tt, v, nd)];
-          PDE::template flux<I>(qn, F, p.g, cp);
+          for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e, v)];
+          PDE::template flux_pub<I>(qn, F, p.g, cp);
 #pragma unroll
           for (int k = 0; k < n; ++k)
 #pragma unroll
             for (int v = 0; v < M; ++v) out[k][v] = fma(p.t.D[k][j], F[v], out[k][v]);
         }
+        // axis sums: every read of the pencil before any write, so the reads
+        // are not serialised behind possibly aliasing stores
+        if constexpr (I > 0) {
 #pragma unroll
-        for (int k = 0; k < n; ++k) {
-          const int nd = pencil_node<n, I>(b, k);
+          for (int k = 0; k < n; ++k)
 #pragma unroll
-          for (int v = 0; v < M; ++v) {
-            if constexpr (I == 0) Rs[K::lidx(tt, v, nd)] = out[k][v];
-            else Rs[K::lidx(tt, v, nd)] += out[k][v];
-          }
+            for (int v = 0; v < M; ++v) out[k][v] += Rs[K::template lidx_e<S>(e0 + k * sI, v)];
         }
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+#pragma unroll
+          for (int v = 0; v < M; ++v) Rs[K::template lidx_e<S>(e0 + k * sI, v)] = out[k][v];
       };
-      if constexpr (ns * NF == NS) {
-        pencil(a / NF, a % NF);                  // exactly one task per thread
-      } else {
-        for (int task = a; task < ns * NF; task += NS) pencil(task / NF, task % NF);
-      }
+      if (ns * NF == NS || a < ns * NF) pencil(e0_of(NS_, I_));   // at most one task per thread
       __syncthreads();
     });
   };
@@ -175,11 +265,11 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
     // pencil, contract with D, keep the result in registers.
     auto pencils = [&](auto NS_, auto& out) {
       constexpr int ns = decltype(NS_)::value;
-      const int tt = (ns * NF == NS) ? a / NF : 0;
-      const int b = (ns * NF == NS) ? a % NF : a;
-      const bool act = (ns * NF == NS) || a < NF;
+      const bool act = (ns * NF == NS) || a < ns * NF;
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
+        constexpr int sI = ipow(n, I);
+        const int e0 = e0_of(NS_, I_);
 #pragma unroll
         for (int k = 0; k < n; ++k)
 #pragma unroll
@@ -187,11 +277,11 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
         if (act) {
 #pragma unroll
           for (int j = 0; j < n; ++j) {
-            const int nd = pencil_node<n, I>(b, j);
+            const int e = e0 + j * sI;
             Real qn[M], F[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) qn[v] = Qs[K::lidx(tt, v, nd)];
-            PDE::template flux<I>(qn, F, p.g, cp);
+            for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e, v)];
+            PDE::template flux_pub<I>(qn, F, p.g, cp);
 #pragma unroll
             for (int k = 0; k < n; ++k)
 #pragma unroll
@@ -203,15 +293,19 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         if (act) {
+          constexpr int sI = ipow(n, I);
+          const int e0 = e0_of(NS_, I_);
+          // every read of the pencil before any write (see contract)
+          if constexpr (I > 0) {
 #pragma unroll
-          for (int k = 0; k < n; ++k) {
-            const int nd = pencil_node<n, I>(b, k);
+            for (int k = 0; k < n; ++k)
 #pragma unroll
-            for (int v = 0; v < M; ++v) {
-              if constexpr (I == 0) Qs[K::lidx(tt, v, nd)] = out[I][k][v];
-              else Qs[K::lidx(tt, v, nd)] += out[I][k][v];
-            }
+              for (int v = 0; v < M; ++v) out[I][k][v] += Qs[K::template lidx_e<S>(e0 + k * sI, v)];
           }
+#pragma unroll
+          for (int k = 0; k < n; ++k)
+#pragma unroll
+            for (int v = 0; v < M; ++v) Qs[K::template lidx_e<S>(e0 + k * sI, v)] = out[I][k][v];
         }
         __syncthreads();
       });
@@ -322,44 +416,43 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
       for (int v = 0; v < M; ++v) Fb[v * NS + a] = fb[v];
     }
     __syncthreads();
-    for (int b = a; b < NF; b += NS) {
-      Real* tr = p.tr + cs * K::TRACE_ELEMS;
-      Real* tL = tr + (int64_t)(2 * I) * K::NQ * NF * M + b * M;
-      Real* tR = tr + (int64_t)(2 * I + 1) * K::NQ * NF * M + b * M;
-      // one variable at a time keeps n + 4 doubles live
+    // one (variable, face node) pair per task: traces of q and F_I on both
+    // faces normal to I, and the Kv contraction of F_I along the pencil
+    for (int task = a; task < M * NF; task += NS) {
+      const int v = task / NF, b = task - v * NF;
+      double fv[n], vol[n], qL = 0.0, qR = 0.0, fL = 0.0, fR = 0.0;
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-        double fv[n], vol[n], qL = 0.0, qR = 0.0, fL = 0.0, fR = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const int nd = pencil_node<n, I>(b, j);
+        fv[j] = Fb[v * NS + nd];
+        const double qv = Qb[v * NS + nd];
+        qL += p.t.FL[j] * qv;
+        qR += p.t.FR[j] * qv;
+        fL += p.t.FL[j] * fv[j];
+        fR += p.t.FR[j] * fv[j];
+      }
 #pragma unroll
-        for (int j = 0; j < n; ++j) {
-          const int nd = pencil_node<n, I>(b, j);
-          fv[j] = Fb[v * NS + nd];
-          const double qv = Qb[v * NS + nd];
-          qL += p.t.FL[j] * qv;
-          qR += p.t.FR[j] * qv;
-          fL += p.t.FL[j] * fv[j];
-          fR += p.t.FR[j] * fv[j];
-        }
+      for (int k = 0; k < n; ++k) {
+        double sacc = 0.0;
 #pragma unroll
-        for (int k = 0; k < n; ++k) {
-          double sacc = 0.0;
+        for (int j = 0; j < n; ++j) sacc += p.t.Kv[k][j] * fv[j];
+        vol[k] = sacc;
+      }
+      if constexpr (I > 0) {       // every read before any write
 #pragma unroll
-          for (int j = 0; j < n; ++j) sacc += p.t.Kv[k][j] * fv[j];
-          vol[k] = sacc;
-        }
+        for (int k = 0; k < n; ++k) vol[k] += Vs[v * NS + pencil_node<n, I>(b, k)];
+      }
 #pragma unroll
-        for (int k = 0; k < n; ++k) {
-          const int nd = pencil_node<n, I>(b, k);
-          if constexpr (I == 0) Vs[v * NS + nd] = vol[k];
-          else Vs[v * NS + nd] += vol[k];
-        }
-        if (live) {
-          tL[v] = (Real)qL;
-          tR[v] = (Real)qR;
-          if constexpr (K::NQ == 2) {
-            tL[NF * M + v] = (Real)fL;
-            tR[NF * M + v] = (Real)fR;
-          }
+      for (int k = 0; k < n; ++k) Vs[v * NS + pencil_node<n, I>(b, k)] = vol[k];
+      if (live) {
+        Real* tr = p.tr + cs * K::TRACE_ELEMS + b * M + v;
+        Real* tL = tr + (int64_t)(2 * I) * K::NQ * NF * M;
+        Real* tR = tr + (int64_t)(2 * I + 1) * K::NQ * NF * M;
+        tL[0] = (Real)qL;
+        tR[0] = (Real)qR;
+        if constexpr (K::NQ == 2) {
+          tL[NF * M] = (Real)fL;
+          tR[NF * M] = (Real)fR;
         }
       }
     }

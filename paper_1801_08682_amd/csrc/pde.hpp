@@ -35,11 +35,13 @@ __device__ __forceinline__ float rcp(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
-// AUX > 0: the PDE caches one per-node value (aux) next to the state so that
-// the per-axis fluxes of a node can share it (Euler: 1/rho).
+// Publish form: the predictor's node threads hand the pencil threads
+// w = pub(q) instead of q, and the pencils evaluate F_I = flux_pub<I>(w).
+// Euler publishes the primitive state (rho, u, p), so the d fluxes of a
+// space-time node share one division; the linear PDEs publish q itself.
 template <int D>
 struct Advection {
-  static constexpr int M = 1, NPAR = 0, AUX = 0;
+  static constexpr int M = 1, NPAR = 0;
   static constexpr bool LINEAR = true;
   template <class T> struct CP { };
   template <class T> __device__ static inline CP<T> cell(const double*) { return {}; }
@@ -47,10 +49,11 @@ struct Advection {
   __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>&) {
     F[0] = g.c[I] * q[0];
   }
-  template <class T> __device__ static inline T aux(const T*) { return T(0); }
+  template <class T>
+  __device__ static inline void pub(const T* q, T* w, const Gconst<T>&) { w[0] = q[0]; }
   template <int I, class T>
-  __device__ static inline void flux_aux(const T* q, T, T* F, const Gconst<T>& g, const CP<T>& cp) {
-    flux<I>(q, F, g, cp);
+  __device__ static inline void flux_pub(const T* w, T* F, const Gconst<T>& g, const CP<T>& cp) {
+    flux<I>(w, F, g, cp);
   }
   template <int I, class T>
   __device__ static inline T speed(const T*, const Gconst<T>& g, const CP<T>&) {
@@ -75,7 +78,7 @@ struct Advection {
 // g.c[0] = gamma, g.c[1] = gamma - 1
 template <int D>
 struct Euler {
-  static constexpr int M = D + 2, NPAR = 0, AUX = 1;
+  static constexpr int M = D + 2, NPAR = 0;
   static constexpr bool LINEAR = false;
   template <class T> struct CP { };
   template <class T> __device__ static inline CP<T> cell(const double*) { return {}; }
@@ -86,13 +89,32 @@ struct Euler {
     for (int k = 1; k < D; ++k) jj += q[1 + k] * q[1 + k];
     return g.c[1] * (q[D + 1] - T(0.5) * jj * ir);
   }
-  template <class T> __device__ static inline T aux(const T* q) { return rcp(q[0]); }
+  // g.c = (gamma, gamma - 1, gamma / (gamma - 1))
+  template <class T>
+  __device__ static inline void pub(const T* q, T* w, const Gconst<T>& g) {
+    const T ir = rcp(q[0]);
+    w[0] = q[0];
+#pragma unroll
+    for (int k = 0; k < D; ++k) w[1 + k] = q[1 + k] * ir;
+    w[D + 1] = pressure(q, ir, g);
+  }
+  // F_I from (rho, u, p): rho u_I, rho u_I u + p e_I, u_I (E + p) with
+  // E + p = gamma/(gamma-1) p + rho |u|^2 / 2.
   template <int I, class T>
-  __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>& cp) {
-    flux_aux<I>(q, rcp(q[0]), F, g, cp);
+  __device__ static inline void flux_pub(const T* w, T* F, const Gconst<T>& g, const CP<T>&) {
+    const T m = w[0] * w[1 + I];
+    T uu = w[1] * w[1];
+#pragma unroll
+    for (int k = 1; k < D; ++k) uu = fma(w[1 + k], w[1 + k], uu);
+    F[0] = m;
+#pragma unroll
+    for (int k = 0; k < D; ++k) F[1 + k] = m * w[1 + k];
+    F[1 + I] += w[D + 1];
+    F[D + 1] = w[1 + I] * fma(T(0.5) * w[0], uu, g.c[2] * w[D + 1]);
   }
   template <int I, class T>
-  __device__ static inline void flux_aux(const T* q, T ir, T* F, const Gconst<T>& g, const CP<T>&) {
+  __device__ static inline void flux(const T* q, T* F, const Gconst<T>& g, const CP<T>&) {
+    const T ir = rcp(q[0]);
     const T p = pressure(q, ir, g);
     const T ui = q[1 + I] * ir;
     F[0] = q[1 + I];
@@ -116,7 +138,7 @@ struct Euler {
     const T ir = rcp(q[0]);
     return q[0] > T(0) && pressure(q, ir, g) > T(0);
   }
-  // Reverse mode of flux_aux through ir = 1/rho, u_I = j_I ir,
+  // Reverse mode of flux through ir = 1/rho, u_I = j_I ir,
   // p = (gamma-1)(E - |j|^2 ir / 2).
   template <int I>
   __device__ static inline void flux_adj(const double* q, const double* Fb, double* qb, double*,
@@ -178,7 +200,7 @@ struct Euler {
 // Q = (p, u_1..u_D), F_i = (c^2 u_i, p e_i).
 template <int D>
 struct Acoustic {
-  static constexpr int M = D + 1, NPAR = 1, AUX = 0;
+  static constexpr int M = D + 1, NPAR = 1;
   static constexpr bool LINEAR = true;
   template <class T> struct CP { T c, K; };
   template <class T> __device__ static inline CP<T> cell(const double* par) {
@@ -191,10 +213,14 @@ struct Acoustic {
 #pragma unroll
     for (int k = 0; k < D; ++k) F[1 + k] = (k == I) ? q[0] : T(0);
   }
-  template <class T> __device__ static inline T aux(const T*) { return T(0); }
+  template <class T>
+  __device__ static inline void pub(const T* q, T* w, const Gconst<T>&) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) w[v] = q[v];
+  }
   template <int I, class T>
-  __device__ static inline void flux_aux(const T* q, T, T* F, const Gconst<T>& g, const CP<T>& cp) {
-    flux<I>(q, F, g, cp);
+  __device__ static inline void flux_pub(const T* w, T* F, const Gconst<T>& g, const CP<T>& cp) {
+    flux<I>(w, F, g, cp);
   }
   template <int I, class T>
   __device__ static inline T speed(const T*, const Gconst<T>&, const CP<T>& cp) { return cp.c; }
@@ -227,7 +253,7 @@ struct Acoustic {
 template <int D>
 struct Elastic {
   static constexpr int NS_ = (D == 3) ? 6 : 3;
-  static constexpr int M = D + NS_, NPAR = 3, AUX = 0;
+  static constexpr int M = D + NS_, NPAR = 3;
   static constexpr bool LINEAR = true;
   template <class T> struct CP { T irho, lam, mu, cp; };
   template <class T> __device__ static inline CP<T> cell(const double* par) {
@@ -262,10 +288,14 @@ struct Elastic {
       F[D + s] = -t;
     }
   }
-  template <class T> __device__ static inline T aux(const T*) { return T(0); }
+  template <class T>
+  __device__ static inline void pub(const T* q, T* w, const Gconst<T>&) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) w[v] = q[v];
+  }
   template <int I, class T>
-  __device__ static inline void flux_aux(const T* q, T, T* F, const Gconst<T>& g, const CP<T>& cp) {
-    flux<I>(q, F, g, cp);
+  __device__ static inline void flux_pub(const T* w, T* F, const Gconst<T>& g, const CP<T>& cp) {
+    flux<I>(w, F, g, cp);
   }
   template <int I, class T>
   __device__ static inline T speed(const T*, const Gconst<T>&, const CP<T>& cp) { return cp.cp; }
