@@ -74,6 +74,7 @@ typedef struct {
   int32_t picard_iters;   /* R; 0 selects N + 1 */
   int32_t precision;      /* adg_precision */
   int32_t adjoint;        /* nonzero: reserve workspace for adg_step_adjoint (FP64 only) */
+  int32_t fused;          /* nonzero: reserve workspace for adg_run_fused */
 } adg_config;
 
 typedef struct adg_ctx adg_ctx;
@@ -86,7 +87,9 @@ typedef struct adg_ctx adg_ctx;
  *                     extrapolate, reduced to one time value per face node)
  *                     plus reduction scratch; with cfg->adjoint also a copy
  *                     of Q, the hull's bars and per-block Picard scratch
- *                     (at most 2048 blocks, at most 2 GiB).
+ *                     (at most 2048 blocks, at most 2 GiB); with cfg->fused a
+ *                     second Q~ buffer, a second hull and 256 bytes of time
+ *                     step state.
  * Any output pointer may be NULL.  Returns INVALID_ARG / UNSUPPORTED as above. */
 adg_status adg_query(const adg_config* cfg, int64_t* dofs_per_cell, int64_t* params_per_cell,
                      int64_t* workspace_bytes);
@@ -112,7 +115,8 @@ adg_status adg_predict(adg_ctx* ctx, double* d_Q, const double* d_params, const 
  * adg_predict, add the face term of Eq. (2) to Q~ in place, and record the
  * per-block maximum wave speed of the new state for adg_cfl_dt.
  * d_flag (nullable) is OR-ed with 1 on a non-finite state and 2 on a
- * non-physical one; the caller zeroes it. */
+ * non-physical one (or a face trace whose wave speed is not a real number);
+ * the caller zeroes it. */
 adg_status adg_correct(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt,
                        int32_t* d_flag);
 
@@ -130,6 +134,43 @@ adg_status adg_wave_speed(adg_ctx* ctx, const double* d_Q, const double* d_param
  * adg_wave_speed into *d_lambda_max (nullable) and set, on the device,
  * *d_dt = cfl * h / (d (2N + 1) lambda_max).  No host synchronisation. */
 adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_dt);
+
+/* Shifted, fused and optimistic time stepping (Sec. 5, Techniques 3-5;
+ * Alg. 2): advance Q by nsteps steps with one sweep per step.  A sweep runs,
+ * per cell, the Riemann solves and corrector of step k (Delta T_old) and at
+ * once the predictor of step k+1 on the new state (Delta T_new), so Q is read
+ * and written once per step.  The admissible dt of the new states,
+ *   dt_adm = cfl * h / (d (2N+1) lambda_max),
+ * is known only after the sweep; if dt_adm < Delta T_new the sweep's
+ * predictors are rerun with c_dt * dt_adm (on the device, no host
+ * synchronisation).  Then Delta T_old <- Delta T_new and Delta T_new <-
+ * (Delta T_old + c_dt dt_adm) / 2 (creeping != 0) or c_dt dt_adm.  The first
+ * predictor uses c_dt * dt_adm(Q(T)).  The paper uses c_dt = 0.99; c_dt > 1
+ * forces a rerun after every sweep.
+ *   d_Q       in: Q(T); out: Q after nsteps steps (also used as a ping-pong
+ *             buffer during the run);
+ *   d_dt_used (nullable) out: the nsteps time steps taken, in order;
+ *   d_reruns  (nullable) out: number of predictor reruns (int32);
+ *   d_flag    (nullable) as in adg_correct.
+ * Needs a context created with cfg->fused != 0 (else ADG_ERR_WORKSPACE);
+ * nsteps >= 1, cfl > 0, c_dt > 0 (else ADG_ERR_INVALID_ARG).  Overwrites the
+ * hull and the per-block maxima of the workspace. */
+adg_status adg_run_fused(adg_ctx* ctx, double* d_Q, const double* d_params, int32_t nsteps,
+                         double cfl, double c_dt, int32_t creeping, double* d_dt_used,
+                         int32_t* d_reruns, int32_t* d_flag);
+
+/* adg_run_fused in three parts, for callers that drive the sweeps:
+ * adg_fused_begin (dt from Q(T), predictor of step 1; d_dt_used holds at most
+ * dt_capacity steps, later ones are not recorded), then one adg_fused_sweep
+ * per further step, then adg_fused_end (corrector of the last step into the
+ * d_Q given to begin).  Arguments and errors as for adg_run_fused; sweep and
+ * end without a begun run return ADG_ERR_INVALID_ARG.  Between begin and end
+ * d_Q holds an intermediate (a predicted Q~), not a state. */
+adg_status adg_fused_begin(adg_ctx* ctx, double* d_Q, const double* d_params, double cfl,
+                           double c_dt, int32_t creeping, double* d_dt_used, int32_t dt_capacity,
+                           int32_t* d_reruns, int32_t* d_flag);
+adg_status adg_fused_sweep(adg_ctx* ctx);
+adg_status adg_fused_end(adg_ctx* ctx);
 
 /* Reverse mode of one adg_step with dt held fixed (the discrete adjoint of
  * Eq. (5)/(6) including the Picard iterations and the Rusanov maximum; the

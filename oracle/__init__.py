@@ -30,9 +30,10 @@ pde          fluxes and wave speeds (advection, Euler, acoustics, elasticity)
 step         predictor, traces, Rusanov, corrector, time step; sampled step
 diagnostics  L2 norms, conserved totals, point evaluation, kinetic energy
 adjoint      reverse mode through a rollout (torch autograd), functionals
+fused        shifted, fused, optimistic time stepping (Alg. 2)
 
 Every function works on float64 torch CPU tensors so that torch.autograd gives
 an adjoint that shares nothing with the hand-written GPU adjoint.
 """
 
-from . import tables, pde, step, diagnostics  # noqa: F401
+from . import tables, pde, step, diagnostics, fused  # noqa: F401

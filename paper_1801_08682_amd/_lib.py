@@ -15,7 +15,8 @@ STATUS_NAMES = {0: "ADG_OK", 1: "ADG_ERR_INVALID_ARG", 2: "ADG_ERR_UNSUPPORTED",
                 3: "ADG_ERR_DEVICE", 4: "ADG_ERR_WORKSPACE"}
 
 EXPORTS = ["adg_query", "adg_init", "adg_predict", "adg_correct", "adg_step",
-           "adg_wave_speed", "adg_cfl_dt", "adg_step_adjoint", "adg_destroy",
+           "adg_wave_speed", "adg_cfl_dt", "adg_step_adjoint", "adg_run_fused", "adg_fused_begin",
+           "adg_fused_sweep", "adg_fused_end", "adg_destroy",
            "adg_last_error", "adg_version"]
 
 
@@ -28,7 +29,8 @@ class AdgConfig(ctypes.Structure):
                 ("pde_param", ctypes.c_double * 4),
                 ("picard_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32),
-                ("adjoint", ctypes.c_int32)]
+                ("adjoint", ctypes.c_int32),
+                ("fused", ctypes.c_int32)]
 
 
 class AdgError(RuntimeError):
@@ -60,6 +62,12 @@ def load(path=LIB_PATH):
         "adg_wave_speed": [vp, dp, dp],
         "adg_cfl_dt": [vp, ctypes.c_double, dp, dp],
         "adg_step_adjoint": [vp, dp, dp, dp, dp, dp],
+        "adg_run_fused": [vp, dp, dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_int32, dp, ip, ip],
+        "adg_fused_begin": [vp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, dp,
+                            ctypes.c_int32, ip, ip],
+        "adg_fused_sweep": [vp],
+        "adg_fused_end": [vp],
         "adg_destroy": [vp],
     }
     for name, args in sig.items():
@@ -82,7 +90,7 @@ def check(status, ctx=None):
 
 
 def make_config(dim, order, n_cells, length, pde, pde_param=(), picard_iters=0, precision=0,
-                adjoint=False):
+                adjoint=False, fused=False):
     c = AdgConfig()
     c.dim = dim
     c.order = order
@@ -99,6 +107,7 @@ def make_config(dim, order, n_cells, length, pde, pde_param=(), picard_iters=0, 
     c.picard_iters = picard_iters
     c.precision = precision
     c.adjoint = 1 if adjoint else 0
+    c.fused = 1 if fused else 0
     return c
 
 

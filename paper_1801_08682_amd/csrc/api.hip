@@ -20,6 +20,7 @@ struct Layout {
   int64_t trace_off = 0, trace_bytes = 0;
   int64_t partial_off = 0, partial_count = 0;
   int64_t qtmp_off = 0, tb_off = 0, slots_off = 0, nslots = 0;
+  int64_t q2_off = 0, tr2_off = 0, fz_off = 0;   // fused stepping: second Q~, second hull, dt state
   int64_t total = 0;
 };
 
@@ -117,6 +118,12 @@ Layout layout_of(const adg_config* c, const adg::Launchers* L) {
     l.nslots = adjoint_slots(cells, slot);
     l.total = l.slots_off + align256(l.nslots * slot);
   }
+  if (c->fused) {
+    l.q2_off = l.total;
+    l.tr2_off = l.q2_off + align256(cells * L->qdofs_per_cell * 8);
+    l.fz_off = l.tr2_off + align256(cells * L->trace_bytes_per_cell);
+    l.total = l.fz_off + 256;
+  }
   return l;
 }
 
@@ -144,6 +151,66 @@ __global__ void __launch_bounds__(256) k_dt(const double* partial, int64_t cnt, 
   }
 }
 
+// Time step state of the fused scheme (device memory, in the workspace).
+struct FzState {
+  double dt_corr;     // dt of the next sweep's corrector (the dt its predictors used)
+  double dt_stp;      // dt of the next sweep's predictors (Delta T_new)
+  double dtc_rerun;   // rerun: the corrector's dt (unchanged)
+  double dts_rerun;   // rerun: the predictors' reset dt
+  double lam;         // largest wave speed of the last sweep's new states
+  double dt_adm;      // the admissible dt of those states
+  int32_t rerun;      // 1: the last sweep's predictors must be rerun
+  int32_t reruns;     // reruns so far
+};
+
+// Optimistic time step control (Sec. 5 Technique 5; Alg. 2), one block.
+// dt_adm = coef / lambda_max with coef = C h / (d (2N+1)).
+//  mode 0 (start, lambda of Q^0): dt_corr = dt_stp = c_dt dt_adm.
+//  mode 1 (after sweep k: corrector of step k, predictors of step k+1):
+//    dt_used[k-1] = dt_corr; if dt_adm < dt_stp the predictors overshot:
+//    rerun them with dts_rerun = c_dt dt_adm (corrector unchanged).  Then
+//    Delta T_old = dt_stp (as finally used), Delta T_new = the creeping
+//    average (Delta T_old + c_dt dt_adm) / 2, or c_dt dt_adm.
+//  mode 2 (before the last corrector): dt_used[k-1] = dt_corr.
+__global__ void __launch_bounds__(256) k_fz_dt(const double* partial, int64_t cnt, double coef,
+                                               double c_dt, int creeping, int mode, FzState* st,
+                                               double* dt_used, int64_t k, int32_t* reruns_out) {
+  __shared__ double red[4];
+  double m = 0.0;
+  if (mode != 2)
+    for (int64_t i = threadIdx.x; i < cnt; i += 256) m = fmax(m, partial[i]);
+  m = adg::block_max<256>(m, red);
+  if (threadIdx.x != 0) return;
+  if (mode == 2) {
+    if (dt_used) dt_used[k - 1] = st->dt_corr;
+    return;
+  }
+  const double adm = coef / m;
+  st->lam = m;
+  st->dt_adm = adm;
+  if (mode == 0) {
+    st->dt_corr = c_dt * adm;
+    st->dt_stp = c_dt * adm;
+    st->rerun = 0;
+    st->reruns = 0;
+  } else {
+    if (dt_used) dt_used[k - 1] = st->dt_corr;
+    double used = st->dt_stp;
+    if (adm < used) {
+      st->rerun = 1;
+      st->reruns += 1;
+      st->dtc_rerun = st->dt_corr;
+      st->dts_rerun = c_dt * adm;
+      used = c_dt * adm;
+    } else {
+      st->rerun = 0;
+    }
+    st->dt_corr = used;
+    st->dt_stp = creeping ? 0.5 * (used + c_dt * adm) : c_dt * adm;
+  }
+  if (reruns_out) *reruns_out = st->reruns;
+}
+
 }  // namespace
 
 struct adg_ctx {
@@ -159,6 +226,19 @@ struct adg_ctx {
   int R = 1;
   double gp[4] = {0, 0, 0, 0};
   std::string err;
+  struct FusedRun {             // host side of a fused run (adg_fused_begin .. end)
+    bool active = false;
+    double* Q = nullptr;
+    const double* params = nullptr;
+    int32_t* flag = nullptr;
+    double* dt_used = nullptr;
+    int32_t dt_capacity = 0;
+    int32_t* reruns = nullptr;
+    double coef = 0.0, c_dt = 1.0;
+    int32_t creeping = 1;
+    int cur = 1, curt = 0;      // (Q~, hull) of the step in flight
+    int32_t k = 0;              // steps begun
+  } fz;
 
   adg::LaunchArgs args() {
     adg::LaunchArgs a;
@@ -313,6 +393,18 @@ adg_status adg_wave_speed(adg_ctx* ctx, const double* d_Q, const double* d_param
   return ctx->launched(ctx->L->wave_speed(a), "wave_speed");
 }
 
+// Stage the recorded per-block maxima for a one-block reduction.
+static void stage_partial(adg_ctx* ctx, const double** part, int64_t* cnt) {
+  *part = reinterpret_cast<const double*>(ctx->ws + ctx->lay.partial_off);
+  *cnt = ctx->n_partial_used;
+  if (*cnt > 4096) {
+    double* stage = reinterpret_cast<double*>(ctx->ws + ctx->lay.partial_off) + ctx->lay.partial_count - 256;
+    hipLaunchKernelGGL(k_max256, dim3(256), dim3(256), 0, ctx->stream, *part, *cnt, stage);
+    *part = stage;
+    *cnt = 256;
+  }
+}
+
 adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_dt) {
   if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
   if (!(cfl > 0.0)) return ctx->fail(ADG_ERR_INVALID_ARG, "cfl must be positive");
@@ -320,16 +412,128 @@ adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_
   if (ctx->n_partial_used <= 0)
     return ctx->fail(ADG_ERR_INVALID_ARG, "no wave speeds recorded (call adg_correct or adg_wave_speed)");
   const double coef = cfl * ctx->h / (ctx->cfg.dim * (2.0 * ctx->cfg.order + 1.0));
-  const double* part = reinterpret_cast<const double*>(ctx->ws + ctx->lay.partial_off);
-  int64_t cnt = ctx->n_partial_used;
-  if (cnt > 4096) {
-    double* stage = reinterpret_cast<double*>(ctx->ws + ctx->lay.partial_off) + ctx->lay.partial_count - 256;
-    hipLaunchKernelGGL(k_max256, dim3(256), dim3(256), 0, ctx->stream, part, cnt, stage);
-    part = stage;
-    cnt = 256;
-  }
+  const double* part = nullptr;
+  int64_t cnt = 0;
+  stage_partial(ctx, &part, &cnt);
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, part, cnt, coef, d_lambda_max, d_dt);
   return ctx->launched((int)hipGetLastError(), "cfl_dt");
+}
+
+static void fz_dt(adg_ctx* ctx, int mode) {
+  adg_ctx::FusedRun& r = ctx->fz;
+  FzState* st = reinterpret_cast<FzState*>(ctx->ws + ctx->lay.fz_off);
+  const double* part = nullptr;
+  int64_t cnt = 0;
+  if (mode != 2) stage_partial(ctx, &part, &cnt);
+  double* rec = (r.dt_used && r.k <= r.dt_capacity) ? r.dt_used : nullptr;
+  hipLaunchKernelGGL(k_fz_dt, dim3(1), dim3(256), 0, ctx->stream, part, cnt, r.coef, r.c_dt,
+                     r.creeping, mode, st, rec, (int64_t)r.k, r.reruns);
+}
+
+adg_status adg_fused_begin(adg_ctx* ctx, double* d_Q, const double* d_params, double cfl, double c_dt,
+                           int32_t creeping, double* d_dt_used, int32_t dt_capacity,
+                           int32_t* d_reruns, int32_t* d_flag) {
+  double one = 1.0;
+  adg_status s = check_state(ctx, d_Q, d_params, &one);
+  if (s != ADG_OK) return s;
+  if (!(cfl > 0.0) || !(c_dt > 0.0)) return ctx->fail(ADG_ERR_INVALID_ARG, "cfl and c_dt must be positive");
+  if (ctx->lay.fz_off <= 0)
+    return ctx->fail(ADG_ERR_WORKSPACE, "fused workspace not reserved (set adg_config.fused)");
+  adg_ctx::FusedRun& r = ctx->fz;
+  r = adg_ctx::FusedRun();
+  r.Q = d_Q;
+  r.params = d_params;
+  r.flag = d_flag;
+  r.dt_used = d_dt_used;
+  r.dt_capacity = d_dt_used ? dt_capacity : 0;
+  r.reruns = d_reruns;
+  r.coef = cfl * ctx->h / (ctx->cfg.dim * (2.0 * ctx->cfg.order + 1.0));
+  r.c_dt = c_dt;
+  r.creeping = creeping;
+  FzState* st = reinterpret_cast<FzState*>(ctx->ws + ctx->lay.fz_off);
+  adg::LaunchArgs a = ctx->args();
+  a.params = d_params;
+  a.flag = d_flag;
+  // dt from the speeds of Q(T), then the predictor of step 1: Q -> (Q2, hull 0)
+  a.Qc = d_Q;
+  if ((s = ctx->launched(ctx->L->wave_speed(a), "fused: wave_speed")) != ADG_OK) return s;
+  fz_dt(ctx, 0);
+  a.Q = d_Q;
+  a.qin = d_Q;
+  a.qout = reinterpret_cast<double*>(ctx->ws + ctx->lay.q2_off);
+  a.traces = ctx->ws + ctx->lay.trace_off;
+  a.dt = &st->dt_stp;
+  if ((s = ctx->launched(ctx->L->predict(a), "fused: predict")) != ADG_OK) return s;
+  r.cur = 1;
+  r.curt = 0;
+  r.k = 1;
+  r.active = true;
+  return ADG_OK;
+}
+
+adg_status adg_fused_sweep(adg_ctx* ctx) {
+  if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  adg_ctx::FusedRun& r = ctx->fz;
+  if (!r.active) return ctx->fail(ADG_ERR_INVALID_ARG, "no fused run (call adg_fused_begin)");
+  FzState* st = reinterpret_cast<FzState*>(ctx->ws + ctx->lay.fz_off);
+  double* X[2] = {r.Q, reinterpret_cast<double*>(ctx->ws + ctx->lay.q2_off)};
+  void* T[2] = {ctx->ws + ctx->lay.trace_off, ctx->ws + ctx->lay.tr2_off};
+  adg::LaunchArgs a = ctx->args();
+  a.params = r.params;
+  a.flag = r.flag;
+  a.Q = r.Q;
+  a.qin = X[r.cur];
+  a.qout = X[1 - r.cur];
+  a.traces = T[r.curt];
+  a.traces_out = T[1 - r.curt];
+  a.dt = &st->dt_corr;
+  a.dt_pred = &st->dt_stp;
+  adg_status s;
+  if ((s = ctx->launched(ctx->L->fused(a), "fused: sweep")) != ADG_OK) return s;
+  fz_dt(ctx, 1);
+  a.dt = &st->dtc_rerun;
+  a.dt_pred = &st->dts_rerun;
+  a.run_if = &st->rerun;
+  if ((s = ctx->launched(ctx->L->fused(a), "fused: rerun")) != ADG_OK) return s;
+  r.cur = 1 - r.cur;
+  r.curt = 1 - r.curt;
+  r.k += 1;
+  return ADG_OK;
+}
+
+adg_status adg_fused_end(adg_ctx* ctx) {
+  if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  adg_ctx::FusedRun& r = ctx->fz;
+  if (!r.active) return ctx->fail(ADG_ERR_INVALID_ARG, "no fused run (call adg_fused_begin)");
+  FzState* st = reinterpret_cast<FzState*>(ctx->ws + ctx->lay.fz_off);
+  double* X[2] = {r.Q, reinterpret_cast<double*>(ctx->ws + ctx->lay.q2_off)};
+  void* T[2] = {ctx->ws + ctx->lay.trace_off, ctx->ws + ctx->lay.tr2_off};
+  fz_dt(ctx, 2);
+  adg::LaunchArgs a = ctx->args();
+  a.params = r.params;
+  a.flag = r.flag;
+  a.Q = r.Q;
+  a.qin = X[r.cur];
+  a.qout = r.Q;
+  a.traces = T[r.curt];
+  a.dt = &st->dt_corr;
+  r.active = false;
+  return ctx->launched(ctx->L->correct(a), "fused: correct");
+}
+
+adg_status adg_run_fused(adg_ctx* ctx, double* d_Q, const double* d_params, int32_t nsteps,
+                         double cfl, double c_dt, int32_t creeping, double* d_dt_used,
+                         int32_t* d_reruns, int32_t* d_flag) {
+  if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (nsteps < 1) return ctx->fail(ADG_ERR_INVALID_ARG, "nsteps must be at least 1");
+  adg_status s = adg_fused_begin(ctx, d_Q, d_params, cfl, c_dt, creeping, d_dt_used, nsteps,
+                                 d_reruns, d_flag);
+  for (int32_t k = 1; s == ADG_OK && k < nsteps; ++k) s = adg_fused_sweep(ctx);
+  if (s != ADG_OK) {
+    ctx->fz.active = false;
+    return s;
+  }
+  return adg_fused_end(ctx);
 }
 
 adg_status adg_step_adjoint(adg_ctx* ctx, const double* d_Qn, const double* d_params, const double* d_dt,

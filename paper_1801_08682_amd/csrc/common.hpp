@@ -78,6 +78,14 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
 // Everything a launcher needs from the context.
 struct LaunchArgs {
   double* Q = nullptr;
+  // Optional separate input / output of the predictor and corrector (both
+  // default to Q in place) and, for the fused step, the hull it writes, the
+  // predictor's time step and the rerun switch.
+  const double* qin = nullptr;
+  double* qout = nullptr;
+  void* traces_out = nullptr;
+  const double* dt_pred = nullptr;
+  const int32_t* run_if = nullptr;
   const double* Qc = nullptr;       // read-only state (wave speed / adjoint)
   const double* params = nullptr;
   const double* dt = nullptr;
@@ -109,6 +117,7 @@ struct Launchers {
   LaunchFn correct = nullptr;
   LaunchFn wave_speed = nullptr;
   LaunchFn adjoint = nullptr;
+  LaunchFn fused = nullptr;
   int64_t trace_bytes_per_cell = 0;
   int64_t qdofs_per_cell = 0;                  // m (N+1)^d
   int64_t (*adj_slot_doubles)(int R) = nullptr;

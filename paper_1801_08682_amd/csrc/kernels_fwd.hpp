@@ -74,8 +74,10 @@ struct Fwd {
   static constexpr int S = ALIAS ? n : pick_S();
   static constexpr int NB = (n + S - 1) / S;                 // batches per iteration
   static constexpr int PIC_BYTES = (ALIAS ? 1 : 2) * S * NSP * MP * (int)sizeof(Real);
-  static constexpr int FIN_BYTES = 3 * NS * M * 8;
-  static constexpr int CELL_BYTES = ((PIC_BYTES > FIN_BYTES ? PIC_BYTES : FIN_BYTES) + 15) / 16 * 16;
+  static constexpr int FIRST_BYTES = D * NSP * MP * (int)sizeof(Real);   // d flux planes of u
+  static constexpr int FIN_BYTES = (D + 2) * NS * M * 8;                 // Fbar_i, qbar, V
+  static constexpr int max3(int x, int y, int z) { return x > y ? (x > z ? x : z) : (y > z ? y : z); }
+  static constexpr int CELL_BYTES = (max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
   static constexpr int64_t TRACE_ELEMS = 2LL * D * NQ * NF * M;   // per cell
@@ -147,7 +149,8 @@ __device__ __forceinline__ int task_e0(int a) {
 
 template <class K>
 struct PredP {
-  double* Q;
+  const double* Qin;     // Q (cell, node, var)
+  double* Qout;          // Q~ = Q + dt V; may be Qin
   const double* par;
   const double* dt;
   typename K::Real* tr;
@@ -158,28 +161,23 @@ struct PredP {
   KTab<K::n, typename K::Real> t;
 };
 
+// Predictor of one cell, called by all K::NS node threads of the cell (and
+// every thread of the workgroup, for the barriers).  u is this node's state;
+// base is the cell's K::CELL_BYTES of LDS.  Writes the cell's face hull and
+// Q~ = u + dt V (predict, extrapolate, integrateVolume).
 template <class K>
-__global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
+__device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base, int a,
+                                          int64_t cell, bool live, const double (&u)[K::M]) {
   using Real = typename K::Real;
   using PDE = typename K::PDE;
   constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, S = K::S, D = K::D;
   constexpr int NSP = K::NSP;
-  __shared__ __align__(16) unsigned char smem[K::LDS_BYTES];
-
-  const int lc = threadIdx.x / NS;
-  const int a = threadIdx.x - lc * NS;
-  const int64_t cell = (int64_t)blockIdx.x * K::CPB + lc;
-  const bool live = cell < p.ncells;
   const int64_t cs = live ? cell : 0;
-  unsigned char* base = smem + lc * K::CELL_BYTES;
-  Real* Qs = reinterpret_cast<Real*>(base);      // [S][M][NSP]: q of S time slices
-  Real* Rs = Qs + S * NSP * K::MP;               // [S][M][NSP]: sum_i D_i F_i(q)
+  Real* Qs = reinterpret_cast<Real*>(base);      // published slices
+  Real* Rs = Qs + S * NSP * K::MP;               // sum_i D_i F_i of the slices
 
   const double cdt = (*p.dt) * p.inv_h;   // dt / h
   const Real c = (Real)cdt;
-  double u[M];
-#pragma unroll
-  for (int v = 0; v < M; ++v) u[v] = p.Q[(cs * NS + a) * M + v];
   const auto cp = PDE::template cell<Real>(p.par + cs * K::NPAR);
 
   Real q[n][M];
@@ -259,6 +257,48 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
     });
   };
 
+  // First iteration: q = u on every time node, so sum_i D_i F_i(q) is the
+  // same on every slice and P reduces to its row sums.  Every node thread
+  // evaluates its d fluxes of u, then gathers sum_i D_i F_i at its own node
+  // from the d pencils through it (all lanes busy, one barrier).
+  auto first_iteration = [&]() {
+    Real* Fs = reinterpret_cast<Real*>(base);      // [axis][var][node] planes
+    {
+      Real uu[M], w[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) uu[v] = (Real)u[v];
+      PDE::pub(uu, w, p.g);
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        Real F[M];
+        PDE::template flux_pub<I>(w, F, p.g, cp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + a, v)] = F[v];
+      });
+    }
+    __syncthreads();
+    Real rv[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) rv[v] = Real(0);
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      constexpr int sI = ipow(n, I);
+      const int ai = coord<n, I>(a);
+      const int e0 = I * NSP + a - ai * sI;
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        const Real dj = p.t.D[ai][j];
+#pragma unroll
+        for (int v = 0; v < M; ++v) rv[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], rv[v]);
+      }
+    });
+#pragma unroll
+    for (int v = 0; v < M; ++v)
+#pragma unroll
+      for (int t = 0; t < n; ++t) q[t][v] = (Real)u[v] - c * (p.t.Ps[t] * rv[v]);
+    __syncthreads();                                // Fs is reused below
+  };
+
   // ---- predict: Picard iteration q <- u - (dt/h) P sum_i D_i F_i(q) ----
   if constexpr (K::ALIAS) {
     // One pencil per axis per thread and slice: evaluate F_I along the
@@ -311,18 +351,9 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
       });
     };
     Real out[D][n][M];
-    // first iteration: one slice (q = u on every slice)
-    publish(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
-    __syncthreads();
-    pencils(std::integral_constant<int, 1>{}, out);
-#pragma unroll
-    for (int v = 0; v < M; ++v) {
-      const Real rv = Qs[K::lidx(0, v, pa)];
-#pragma unroll
-      for (int t = 0; t < n; ++t) q[t][v] = (Real)u[v] - c * (p.t.Ps[t] * rv);
-    }
+    first_iteration();
     for (int r = 1; r < p.R; ++r) {
-      __syncthreads();                              // slice 0 read by every node above
+      if (r > 1) __syncthreads();                   // every node has read the last rhs
       publish(std::integral_constant<int, 0>{}, std::integral_constant<int, n>{});
       __syncthreads();
       pencils(std::integral_constant<int, n>{}, out);
@@ -341,17 +372,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
       }
     }
   } else {
-  // First iteration: q = u is constant in time, so sum_i D_i F_i(q) is the
-  // same on every slice and P reduces to its row sums (one slice computed).
-  publish(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
-  __syncthreads();
-  contract(std::integral_constant<int, 1>{});
-#pragma unroll
-  for (int v = 0; v < M; ++v) {
-    const Real rv = Rs[K::lidx(0, v, pa)];
-#pragma unroll
-    for (int t = 0; t < n; ++t) q[t][v] = (Real)u[v] - c * (p.t.Ps[t] * rv);
-  }
+  first_iteration();
   for (int r = 1; r < p.R; ++r) {
     Real acc[n][M];
 #pragma unroll
@@ -385,37 +406,43 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   __syncthreads();   // LDS is reused below
 
   // ---- extrapolate + integrateVolume on time averages (float64) ----
-  double* Fb = reinterpret_cast<double*>(base);
-  double* Qb = Fb + NS * M;
-  double* Vs = Qb + NS * M;
+  double* Fb = reinterpret_cast<double*>(base);   // [axis][var][node]: time-averaged F_i
+  double* Qb = Fb + D * NS * M;                   // [var][node]: time-averaged q
+  double* Vs = Qb + NS * M;                       // [var][node]: volume term
   {
-    double qb[M];
+    double fb[D][M];
+#pragma unroll
+    for (int I = 0; I < D; ++I)
+#pragma unroll
+      for (int v = 0; v < M; ++v) fb[I][v] = 0.0;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       double s = 0.0;
 #pragma unroll
       for (int t = 0; t < n; ++t) s += p.t.w[t] * (double)q[t][v];
-      qb[v] = s;
       Qb[v * NS + a] = s;
     }
+#pragma unroll
+    for (int t = 0; t < n; ++t) {
+      Real w[M];
+      PDE::pub(q[t], w, p.g);
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        Real F[M];
+        PDE::template flux_pub<I>(w, F, p.g, cp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) fb[I][v] += p.t.w[t] * (double)F[v];
+      });
+    }
+#pragma unroll
+    for (int I = 0; I < D; ++I)
+#pragma unroll
+      for (int v = 0; v < M; ++v) Fb[(I * M + v) * NS + a] = fb[I][v];
   }
+  __syncthreads();
   static_for<0, D>([&](auto I_) {
     constexpr int I = decltype(I_)::value;
-    {
-      double fb[M];
-#pragma unroll
-      for (int v = 0; v < M; ++v) fb[v] = 0.0;
-#pragma unroll
-      for (int t = 0; t < n; ++t) {
-        Real F[M];
-        PDE::template flux<I>(q[t], F, p.g, cp);
-#pragma unroll
-        for (int v = 0; v < M; ++v) fb[v] += p.t.w[t] * (double)F[v];
-      }
-#pragma unroll
-      for (int v = 0; v < M; ++v) Fb[v * NS + a] = fb[v];
-    }
-    __syncthreads();
+    const double* FbI = Fb + I * M * NS;
     // one (variable, face node) pair per task: traces of q and F_I on both
     // faces normal to I, and the Kv contraction of F_I along the pencil
     for (int task = a; task < M * NF; task += NS) {
@@ -424,7 +451,7 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
 #pragma unroll
       for (int j = 0; j < n; ++j) {
         const int nd = pencil_node<n, I>(b, j);
-        fv[j] = Fb[v * NS + nd];
+        fv[j] = FbI[v * NS + nd];
         const double qv = Qb[v * NS + nd];
         qL += p.t.FL[j] * qv;
         qR += p.t.FR[j] * qv;
@@ -460,8 +487,23 @@ __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   });
   if (live) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) p.Q[(cell * NS + a) * M + v] = u[v] + cdt * Vs[v * NS + a];
+    for (int v = 0; v < M; ++v) p.Qout[(cell * NS + a) * M + v] = u[v] + cdt * Vs[v * NS + a];
   }
+}
+
+template <class K>
+__global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
+  constexpr int M = K::M, NS = K::NS;
+  __shared__ __align__(16) unsigned char smem[K::LDS_BYTES];
+  const int lc = threadIdx.x / NS;
+  const int a = threadIdx.x - lc * NS;
+  const int64_t cell = (int64_t)blockIdx.x * K::CPB + lc;
+  const bool live = cell < p.ncells;
+  const int64_t cs = live ? cell : 0;
+  double u[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) u[v] = p.Qin[(cs * NS + a) * M + v];
+  pred_cell<K>(p, smem + lc * K::CELL_BYTES, a, cell, live, u);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +527,8 @@ __device__ __forceinline__ double block_max(double x, double* red) {
 
 template <class K>
 struct CorrP {
-  double* Q;
+  const double* Qin;     // Q~ (cell, node, var)
+  double* Qout;          // Q(T + dt); may be Qin
   const double* par;
   const double* dt;
   const typename K::Real* tr;
@@ -530,34 +573,29 @@ __device__ __forceinline__ int64_t neighbour(int64_t cell, int i, int dir, const
   return ix + nc[0] * (iy + nc[1] * iz);
 }
 
-template <class K>
-__global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
+// Corrector of one cell with NT threads per cell (t = 0..NT-1; all threads
+// of the workgroup call it, for the barriers).  solveRiemann on the 2d faces
+// (one task per face node), integrateFace + update for node t < NS: the new
+// state of node t in Qn, its largest directional speed folded into lmax and
+// the admissibility flags into bad (2 also for a face trace whose wave speed
+// is not a real number).  lds: the cell's K::CORR_CELL_BYTES.
+template <class K, int NT>
+__device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t, int64_t cell,
+                                          bool live, double (&Qn)[K::M], double& lmax, int& bad) {
   using Real = typename K::Real;
   using PDE = typename K::PDE;
-  constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, CT = K::CT;
-  __shared__ double lds[K::CCPB * K::CORR_CELL_BYTES / 8];
-  __shared__ double red[(K::CTHREADS + 63) / 64];
-
-  const int lc = threadIdx.x / CT;
-  const int t = threadIdx.x - lc * CT;
-  double* lam = lds + lc * (K::CORR_CELL_BYTES / 8);   // [2D][NF]
-  double* Fs = lam + 2 * D * NF;                        // [2D][NF][M]
-  double* sm = Fs + 2 * D * NF * M;                     // [2D]
+  constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, FT = K::FT;
+  constexpr int TPT = (FT + NT - 1) / NT;                 // face tasks per thread
+  double* lam = lds;                                     // [2D][NF]
+  double* Fs = lam + 2 * D * NF;                         // [2D][NF][M]
+  double* sm = Fs + 2 * D * NF * M;                      // [2D]
   const double cdt = (*p.dt) * p.inv_h;
-  const int64_t groups = (p.ncells + K::CCPB - 1) / K::CCPB;
-  double lmax = 0.0;
-  int bad = 0;
-
-  const int64_t grp = xcd_group(groups);
-  if (grp < groups) {
-    const int64_t gc = grp * K::CCPB + lc;
-    const bool live = gc < p.ncells;
-    const int64_t cell = live ? brick_cell(gc, p.nc, p.brick) : 0;
-    // -- solveRiemann on the 2d faces: one thread per (face, face node) --
-    double fh[M], dq[M];
-    const bool ftask = live && t < K::FT;
-    if (ftask) {
-      const int f = t / NF, b = t - f * NF;
+  double fh[TPT][M], dq[TPT][M];
+#pragma unroll
+  for (int r = 0; r < TPT; ++r) {
+    const int task = t + r * NT;
+    if (live && task < FT) {
+      const int f = task / NF, b = task - f * NF;
       const int i = f >> 1, s = f & 1;
       const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
       const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
@@ -590,60 +628,133 @@ __global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
       });
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        fh[v] = 0.5 * (fL[v] + fR[v]);
-        dq[v] = qR[v] - qL[v];
+        fh[r][v] = 0.5 * (fL[v] + fR[v]);
+        dq[r][v] = qR[v] - qL[v];
       }
-      lam[f * NF + b] = l;
+      if (!(l >= 0.0)) bad |= 2;      // a trace without a real wave speed (fmax would skip it)
+      lam[task] = l;
     }
-    __syncthreads();
-    if (live && t < 2 * D) {
-      double s = 0.0;
-      for (int b = 0; b < NF; ++b) s = fmax(s, lam[t * NF + b]);
-      sm[t] = s;
-    }
-    __syncthreads();
-    if (ftask) {
-      const int f = t / NF, b = t - f * NF;
-      const double hs = 0.5 * sm[f];
+  }
+  __syncthreads();
+  if (live && t < 2 * D) {
+    double s = 0.0;
+    for (int b = 0; b < NF; ++b) s = fmax(s, lam[t * NF + b]);
+    sm[t] = s;
+  }
+  __syncthreads();
 #pragma unroll
-      for (int v = 0; v < M; ++v) Fs[(f * NF + b) * M + v] = fh[v] - hs * dq[v];
+  for (int r = 0; r < TPT; ++r) {
+    const int task = t + r * NT;
+    if (live && task < FT) {
+      const double hs = 0.5 * sm[task / NF];
+#pragma unroll
+      for (int v = 0; v < M; ++v) Fs[task * M + v] = fh[r][v] - hs * dq[r][v];
     }
-    __syncthreads();
-    // -- integrateFace + update + calcTimeStep: one thread per node --
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < M; ++v) Qn[v] = 1.0;
+  if (live && t < NS) {
+    const int a = t;
+    const double* Qp = p.Qin + (cell * NS + a) * M;
+#pragma unroll
+    for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      const int k = coord<n, I>(a);
+      const int b = face_node<n, I>(a);
+      const double* Fm = Fs + ((2 * I) * NF + b) * M;
+      const double* Fp = Fs + ((2 * I + 1) * NF + b) * M;
+      const double lr = p.LR[k], ll = p.LL[k];
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qn[v] -= cdt * (lr * Fp[v] - ll * Fm[v]);
+    });
+    const auto pc = PDE::template cell<double>(p.par + cell * K::NPAR);
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      lmax = fmax(lmax, PDE::template speed<I>(Qn, p.g, pc));
+    });
+    if (!PDE::admissible(Qn, p.g, pc)) {
+      bool fin = true;
+#pragma unroll
+      for (int v = 0; v < M; ++v) fin = fin && isfinite(Qn[v]);
+      bad |= fin ? 2 : 1;
+    }
+  }
+}
+
+template <class K>
+__global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
+  constexpr int M = K::M, NS = K::NS, CT = K::CT;
+  __shared__ double lds[K::CCPB * K::CORR_CELL_BYTES / 8];
+  __shared__ double red[(K::CTHREADS + 63) / 64];
+  const int lc = threadIdx.x / CT;
+  const int t = threadIdx.x - lc * CT;
+  const int64_t groups = (p.ncells + K::CCPB - 1) / K::CCPB;
+  double lmax = 0.0;
+  int bad = 0;
+  const int64_t grp = xcd_group(groups);
+  if (grp < groups) {                       // uniform over the workgroup
+    const int64_t gc = grp * K::CCPB + lc;
+    const bool live = gc < p.ncells;
+    const int64_t cell = live ? brick_cell(gc, p.nc, p.brick) : 0;
+    double Qn[M];
+    corr_cell<K, CT>(p, lds + lc * (K::CORR_CELL_BYTES / 8), t, cell, live, Qn, lmax, bad);
     if (live && t < NS) {
-      const int a = t;
-      double Qn[M];
-      double* Qp = p.Q + (cell * NS + a) * M;
-#pragma unroll
-      for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        const int k = coord<n, I>(a);
-        const int b = face_node<n, I>(a);
-        const double* Fm = Fs + ((2 * I) * NF + b) * M;
-        const double* Fp = Fs + ((2 * I + 1) * NF + b) * M;
-        const double lr = p.LR[k], ll = p.LL[k];
-#pragma unroll
-        for (int v = 0; v < M; ++v) Qn[v] -= cdt * (lr * Fp[v] - ll * Fm[v]);
-      });
+      double* Qp = p.Qout + (cell * NS + t) * M;
 #pragma unroll
       for (int v = 0; v < M; ++v) Qp[v] = Qn[v];
-      const auto pc = PDE::template cell<double>(p.par + cell * K::NPAR);
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        lmax = fmax(lmax, PDE::template speed<I>(Qn, p.g, pc));
-      });
-      if (!PDE::admissible(Qn, p.g, pc)) {
-        bool fin = true;
-#pragma unroll
-        for (int v = 0; v < M; ++v) fin = fin && isfinite(Qn[v]);
-        bad |= fin ? 2 : 1;
-      }
     }
   }
   const double bm = block_max<K::CTHREADS>(lmax, red);
   if (threadIdx.x == 0) p.partial[blockIdx.x] = bm;
   if (bad && p.flag) atomicOr(p.flag, bad);
+}
+
+// Shifted and fused step (Sec. 5, Techniques 3 and 4; Alg. 2): per cell the
+// corrector of step n (dt of c) and at once the predictor of step n+1 on the
+// new state (dt of p), so Q is read and written once per step.  Cells follow
+// the corrector's XCD-aware brick walk; K::CPB cells per workgroup with one
+// thread per node.  The per-workgroup speed maxima of the new states go to
+// c.partial.  run_if (nullable): the workgroups leave at once unless
+// *run_if != 0 (the rerun of Technique 5, decided on the device).
+template <class K>
+struct FusedP {
+  CorrP<K> c;
+  PredP<K> p;
+  const int32_t* run_if;
+};
+
+template <class K>
+constexpr int fused_cell_bytes() {
+  constexpr int cb = (K::CORR_CELL_BYTES + 15) / 16 * 16;
+  return K::CELL_BYTES > cb ? K::CELL_BYTES : cb;
+}
+
+template <class K>
+__global__ void __launch_bounds__(K::THREADS) k_fused(const FusedP<K> f) {
+  constexpr int M = K::M, NS = K::NS, FCB = fused_cell_bytes<K>();
+  static_assert(K::CPB * FCB <= 160 * 1024, "fused step LDS exceeds the CU's 160 KiB");
+  __shared__ __align__(16) unsigned char smem[K::CPB * FCB];
+  __shared__ double red[(K::THREADS + 63) / 64];
+  if (f.run_if && *f.run_if == 0) return;   // uniform: no rerun needed
+  const int lc = threadIdx.x / NS;
+  const int a = threadIdx.x - lc * NS;
+  const int64_t groups = (f.c.ncells + K::CPB - 1) / K::CPB;
+  const int64_t grp = xcd_group(groups);
+  const bool act = grp < groups;            // uniform over the workgroup
+  const int64_t gc = grp * K::CPB + lc;
+  const bool live = act && gc < f.c.ncells;
+  const int64_t cell = live ? brick_cell(gc, f.c.nc, f.c.brick) : 0;
+  unsigned char* base = smem + lc * FCB;
+  double Qn[M];
+  double lmax = 0.0;
+  int bad = 0;
+  if (act) corr_cell<K, NS>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
+  const double bm = block_max<K::THREADS>(lmax, red);   // ends with a barrier
+  if (threadIdx.x == 0) f.c.partial[blockIdx.x] = bm;
+  if (bad && f.c.flag) atomicOr(f.c.flag, bad);
+  if (act) pred_cell<K>(f.p, base, a, cell, live, Qn);
 }
 
 template <class K>
@@ -679,10 +790,11 @@ __global__ void __launch_bounds__(256) k_lam(const LamP<K> p) {
 
 // ---------------------------------------------------------------------------
 template <class K>
-int launch_predict(const LaunchArgs& a) {
+PredP<K> pred_params(const LaunchArgs& a) {
   using Real = typename K::Real;
   PredP<K> p;
-  p.Q = a.Q;
+  p.Qin = a.qin ? a.qin : a.Q;
+  p.Qout = a.qout ? a.qout : a.Q;
   p.par = a.params;
   p.dt = a.dt;
   p.tr = reinterpret_cast<Real*>(a.traces);
@@ -691,22 +803,14 @@ int launch_predict(const LaunchArgs& a) {
   p.R = a.R;
   for (int k = 0; k < 4; ++k) p.g.c[k] = (Real)a.gp[k];
   p.t = make_ktab<K::n, Real>(*a.tab);
-  const int64_t blocks = (a.ncells + K::CPB - 1) / K::CPB;
-  hipLaunchKernelGGL(k_pred<K>, dim3((unsigned)blocks), dim3(K::THREADS), 0, a.stream, p);
-  return (int)hipGetLastError();
+  return p;
 }
 
 template <class K>
-int64_t reduce_grid(int64_t groups) {
-  if (groups < 64) return groups;
-  int64_t G = groups < kMaxReduceBlocks ? groups : kMaxReduceBlocks;
-  return G - G % 8;
-}
-
-template <class K>
-int launch_correct(const LaunchArgs& a) {
+CorrP<K> corr_params(const LaunchArgs& a) {
   CorrP<K> p;
-  p.Q = a.Q;
+  p.Qin = a.qin ? a.qin : a.Q;
+  p.Qout = a.qout ? a.qout : a.Q;
   p.par = a.params;
   p.dt = a.dt;
   p.tr = reinterpret_cast<const typename K::Real*>(a.traces);
@@ -721,11 +825,51 @@ int launch_correct(const LaunchArgs& a) {
     p.LR[k] = a.tab->LR[k];
   }
   for (int k = 0; k < 3; ++k) p.brick[k] = a.brick[k];
+  return p;
+}
+
+template <class K>
+int launch_predict(const LaunchArgs& a) {
+  const PredP<K> p = pred_params<K>(a);
+  const int64_t blocks = (a.ncells + K::CPB - 1) / K::CPB;
+  hipLaunchKernelGGL(k_pred<K>, dim3((unsigned)blocks), dim3(K::THREADS), 0, a.stream, p);
+  return (int)hipGetLastError();
+}
+
+template <class K>
+int64_t reduce_grid(int64_t groups) {
+  if (groups < 64) return groups;
+  int64_t G = groups < kMaxReduceBlocks ? groups : kMaxReduceBlocks;
+  return G - G % 8;
+}
+
+template <class K>
+int launch_correct(const LaunchArgs& a) {
+  const CorrP<K> p = corr_params<K>(a);
   const int64_t groups = (a.ncells + K::CCPB - 1) / K::CCPB;
   const int64_t G = 8 * ((groups + 7) / 8);
   if (G > a.n_partial) return (int)hipErrorInvalidValue;
   *a.n_partial_used = G;
   hipLaunchKernelGGL(k_corr<K>, dim3((unsigned)G), dim3(K::CTHREADS), 0, a.stream, p);
+  return (int)hipGetLastError();
+}
+
+// Fused step: corrector with a.dt on (qin, traces), predictor with a.dt_pred
+// writing (qout, traces_out).
+template <class K>
+int launch_fused(const LaunchArgs& a) {
+  FusedP<K> f;
+  f.c = corr_params<K>(a);
+  LaunchArgs b = a;
+  b.dt = a.dt_pred;
+  b.traces = a.traces_out;
+  f.p = pred_params<K>(b);
+  f.run_if = a.run_if;
+  const int64_t groups = (a.ncells + K::CPB - 1) / K::CPB;
+  const int64_t G = 8 * ((groups + 7) / 8);
+  if (G > a.n_partial) return (int)hipErrorInvalidValue;
+  if (!a.run_if) *a.n_partial_used = G;
+  hipLaunchKernelGGL(k_fused<K>, dim3((unsigned)G), dim3(K::THREADS), 0, a.stream, f);
   return (int)hipGetLastError();
 }
 
@@ -751,6 +895,7 @@ Launchers make_fwd_launchers() {
   L.predict = &launch_predict<K>;
   L.correct = &launch_correct<K>;
   L.wave_speed = &launch_wave_speed<K>;
+  L.fused = &launch_fused<K>;
   L.trace_bytes_per_cell = K::TRACE_ELEMS * (int64_t)sizeof(typename K::Real);
   L.qdofs_per_cell = (int64_t)K::NS * K::M;
   return L;

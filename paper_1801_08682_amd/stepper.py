@@ -24,7 +24,7 @@ class Stepper:
     params: (ncells, npar) float64 or None.  dt: float64 device tensor (1,).
     """
 
-    def __init__(self, wl: Workload, device="cuda", stream=None, adjoint=False):
+    def __init__(self, wl: Workload, device="cuda", stream=None, adjoint=False, fused=False):
         self.wl = wl
         self.L = _lib.load()
         self.device = torch.device(device)
@@ -32,7 +32,7 @@ class Stepper:
                                     [wl.length * wl.n_cells[i] / wl.n_cells[0]
                                      for i in range(wl.dim)],
                                     wl.pde, wl.pde_param, wl.picard_iters, wl.precision,
-                                    adjoint)
+                                    adjoint, fused)
         self.dofs_per_cell, self.npar, self.ws_bytes = _lib.query(self.cfg)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.stream(self.stream):
@@ -86,6 +86,32 @@ class Stepper:
             self._p(params_bar)
         self._check(self.L.adg_step_adjoint(self.ctx, self._q(Qn), self._p(params), _ptr(dt),
                                             _ptr(Qbar), _ptr(params_bar)))
+
+    def run_fused(self, Q, params, steps, cfl, c_dt=0.99, creeping=True, flag=None):
+        """Shifted, fused, optimistic stepping (Alg. 2) over `steps` steps.
+        Returns (dt_used (steps,) float64, reruns (1,) int32) device tensors."""
+        dt_used = torch.empty(steps, dtype=torch.float64, device=self.device)
+        reruns = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._check(self.L.adg_run_fused(self.ctx, self._q(Q), self._p(params), int(steps),
+                                         float(cfl), float(c_dt), 1 if creeping else 0,
+                                         _ptr(dt_used), _ptr(reruns), _ptr(flag)))
+        return dt_used, reruns
+
+    def fused_begin(self, Q, params, cfl, c_dt=0.99, creeping=True, capacity=0, flag=None):
+        """adg_fused_begin; returns (dt_used (capacity,), reruns (1,)) device tensors."""
+        dt_used = torch.empty(max(capacity, 1), dtype=torch.float64, device=self.device)
+        reruns = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._check(self.L.adg_fused_begin(self.ctx, self._q(Q), self._p(params), float(cfl),
+                                           float(c_dt), 1 if creeping else 0,
+                                           _ptr(dt_used) if capacity else None, int(capacity),
+                                           _ptr(reruns), _ptr(flag)))
+        return dt_used, reruns
+
+    def fused_sweep(self):
+        self._check(self.L.adg_fused_sweep(self.ctx))
+
+    def fused_end(self):
+        self._check(self.L.adg_fused_end(self.ctx))
 
     def close(self):
         if self.ctx:

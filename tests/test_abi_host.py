@@ -139,3 +139,18 @@ def test_query_adjoint_workspace(L, name):
     assert nslots * slot <= 2 << 30
     c.precision = inputs.FP32
     assert L.adg_query(ctypes.byref(c), None, None, None) in (_lib.ADG_OK, _lib.ADG_ERR_UNSUPPORTED)
+
+
+@pytest.mark.parametrize("name", ["C2", "C4"])
+def test_query_fused_workspace(L, name):
+    """Fused stepping adds a second Q~ buffer, a second hull and 256 bytes of
+    time step state."""
+    wl = inputs.preset(name)
+    _, _, w = _lib.query(cfg_of(wl))
+    c = cfg_of(wl)
+    c.fused = 1
+    _, _, wf = _lib.query(c)
+    n, d, m = wl.n, wl.dim, wl.m
+    nq = 2 if wl.pde == inputs.EULER else 1
+    extra = wl.ncells * m * n ** d * 8 + wl.ncells * 2 * d * nq * m * n ** (d - 1) * 8 + 256
+    assert extra <= wf - w <= extra + 2 * 256
