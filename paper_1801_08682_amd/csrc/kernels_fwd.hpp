@@ -716,8 +716,12 @@ __global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
 // new state (dt of p), so Q is read and written once per step.  Cells follow
 // the corrector's XCD-aware brick walk; K::CPB cells per workgroup with one
 // thread per node.  The per-workgroup speed maxima of the new states go to
-// c.partial.  run_if (nullable): the workgroups leave at once unless
-// *run_if != 0 (the rerun of Technique 5, decided on the device).
+// c.partial.  run_if (nullable): the rerun of Technique 5, decided on the
+// device: the workgroups leave at once unless *run_if != 0, and each takes
+// VB cell groups so that a skipped rerun costs few workgroups; a rerun
+// leaves the maxima and the flag alone (its corrector repeats the sweep's).
+// The sweep itself runs with VB = 1 (no loop, so no registers held across
+// cell groups).
 template <class K>
 struct FusedP {
   CorrP<K> c;
@@ -731,30 +735,50 @@ constexpr int fused_cell_bytes() {
   return K::CELL_BYTES > cb ? K::CELL_BYTES : cb;
 }
 
-template <class K>
+template <class K, int VB>
 __global__ void __launch_bounds__(K::THREADS) k_fused(const FusedP<K> f) {
   constexpr int M = K::M, NS = K::NS, FCB = fused_cell_bytes<K>();
   static_assert(K::CPB * FCB <= 160 * 1024, "fused step LDS exceeds the CU's 160 KiB");
   __shared__ __align__(16) unsigned char smem[K::CPB * FCB];
   __shared__ double red[(K::THREADS + 63) / 64];
-  if (f.run_if && *f.run_if == 0) return;   // uniform: no rerun needed
   const int lc = threadIdx.x / NS;
   const int a = threadIdx.x - lc * NS;
   const int64_t groups = (f.c.ncells + K::CPB - 1) / K::CPB;
-  const int64_t grp = xcd_group(groups);
-  const bool act = grp < groups;            // uniform over the workgroup
-  const int64_t gc = grp * K::CPB + lc;
-  const bool live = act && gc < f.c.ncells;
-  const int64_t cell = live ? brick_cell(gc, f.c.nc, f.c.brick) : 0;
   unsigned char* base = smem + lc * FCB;
-  double Qn[M];
-  double lmax = 0.0;
-  int bad = 0;
-  if (act) corr_cell<K, NS>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
-  const double bm = block_max<K::THREADS>(lmax, red);   // ends with a barrier
-  if (threadIdx.x == 0) f.c.partial[blockIdx.x] = bm;
-  if (bad && f.c.flag) atomicOr(f.c.flag, bad);
-  if (act) pred_cell<K>(f.p, base, a, cell, live, Qn);
+  if constexpr (VB == 1) {                  // the sweep: one cell group, maxima and flag
+    const int64_t grp = xcd_group(groups);
+    const bool act = grp < groups;          // uniform over the workgroup
+    const int64_t gc = grp * K::CPB + lc;
+    const bool live = act && gc < f.c.ncells;
+    const int64_t cell = live ? brick_cell(gc, f.c.nc, f.c.brick) : 0;
+    double Qn[M];
+    double lmax = 0.0;
+    int bad = 0;
+    if (act) corr_cell<K, NS>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
+    const double bm = block_max<K::THREADS>(lmax, red);   // ends with a barrier
+    if (threadIdx.x == 0) f.c.partial[blockIdx.x] = bm;
+    if (bad && f.c.flag) atomicOr(f.c.flag, bad);
+    if (act) pred_cell<K>(f.p, base, a, cell, live, Qn);
+  } else {                                  // the rerun: VB cell groups, skipped if not due
+    if (*f.run_if == 0) return;             // uniform
+    const int64_t span = (groups + 7) / 8;  // cell groups per XCD
+    for (int vb = 0; vb < VB; ++vb) {
+      // virtual workgroup v runs on XCD v mod 8 (gridDim.x is a multiple of 8)
+      const int64_t v = blockIdx.x + (int64_t)vb * gridDim.x;
+      const int64_t grp = (v % 8) * span + v / 8;             // a bijection of [0, 8 span)
+      const bool act = v < 8 * span && grp < groups;          // uniform over the workgroup
+      const int64_t gc = grp * K::CPB + lc;
+      const bool live = act && gc < f.c.ncells;
+      const int64_t cell = live ? brick_cell(gc, f.c.nc, f.c.brick) : 0;
+      double Qn[M];
+      double lmax = 0.0;
+      int bad = 0;
+      if (vb > 0) __syncthreads();          // LDS of the previous cell group read
+      if (act) corr_cell<K, NS>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
+      __syncthreads();                      // corrector LDS read before reuse
+      if (act) pred_cell<K>(f.p, base, a, cell, live, Qn);
+    }
+  }
 }
 
 template <class K>
@@ -866,10 +890,15 @@ int launch_fused(const LaunchArgs& a) {
   f.p = pred_params<K>(b);
   f.run_if = a.run_if;
   const int64_t groups = (a.ncells + K::CPB - 1) / K::CPB;
-  const int64_t G = 8 * ((groups + 7) / 8);
+  const int64_t G = 8 * ((groups + 7) / 8);             // virtual workgroups
   if (G > a.n_partial) return (int)hipErrorInvalidValue;
-  if (!a.run_if) *a.n_partial_used = G;
-  hipLaunchKernelGGL(k_fused<K>, dim3((unsigned)G), dim3(K::THREADS), 0, a.stream, f);
+  if (a.run_if) {      // a rerun takes 16 cell groups per workgroup
+    const int64_t blocks = 8 * ((G / 8 + 15) / 16);
+    hipLaunchKernelGGL((k_fused<K, 16>), dim3((unsigned)blocks), dim3(K::THREADS), 0, a.stream, f);
+  } else {
+    *a.n_partial_used = G;
+    hipLaunchKernelGGL((k_fused<K, 1>), dim3((unsigned)G), dim3(K::THREADS), 0, a.stream, f);
+  }
   return (int)hipGetLastError();
 }
 
