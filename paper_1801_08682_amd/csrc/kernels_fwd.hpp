@@ -590,46 +590,68 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
   double* Fs = lam + 2 * D * NF;                         // [2D][NF][M]
   double* sm = Fs + 2 * D * NF * M;                      // [2D]
   const double cdt = (*p.dt) * p.inv_h;
-  double fh[TPT][M], dq[TPT][M];
+  // Every load of the cell first (the face traces of all of this thread's
+  // tasks and, with several tasks per thread, the node's Q~), so that their
+  // latencies overlap.  With one task per thread (NT >= FT) the Q~ load
+  // waits for the update: fewer live registers, more waves for k_corr.
+  constexpr bool EARLY_Q = TPT > 1;
+  double qL[TPT][M], qR[TPT][M], fL[TPT][M], fR[TPT][M];
+  int64_t cLr[TPT], cRr[TPT];
 #pragma unroll
   for (int r = 0; r < TPT; ++r) {
     const int task = t + r * NT;
+    cLr[r] = cRr[r] = 0;
     if (live && task < FT) {
       const int f = task / NF, b = task - f * NF;
       const int i = f >> 1, s = f & 1;
       const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
       const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
+      cLr[r] = cL;
+      cRr[r] = cR;
       const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b * M;
       const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b * M;
-      double qL[M], qR[M], fL[M], fR[M];
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        qL[v] = (double)trL[v];
-        qR[v] = (double)trR[v];
+        qL[r][v] = (double)trL[v];
+        qR[r][v] = (double)trR[v];
+        if constexpr (K::NQ == 2) {
+          fL[r][v] = (double)trL[NF * M + v];
+          fR[r][v] = (double)trR[NF * M + v];
+        }
       }
-      const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
-      const auto pR = PDE::template cell<double>(p.par + cR * K::NPAR);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < M; ++v) Qn[v] = 1.0;
+  if (EARLY_Q && live && t < NS) {
+    const double* Qp = p.Qin + (cell * NS + t) * M;
+#pragma unroll
+    for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
+  }
+  double fh[TPT][M], dq[TPT][M];
+#pragma unroll
+  for (int r = 0; r < TPT; ++r) {
+    const int task = t + r * NT;
+    if (live && task < FT) {
+      const int f = task / NF;
+      const int i = f >> 1;
+      const auto pL = PDE::template cell<double>(p.par + cLr[r] * K::NPAR);
+      const auto pR = PDE::template cell<double>(p.par + cRr[r] * K::NPAR);
       double l = 0.0;
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         if (i == I) {
-          if constexpr (K::NQ == 2) {
-#pragma unroll
-            for (int v = 0; v < M; ++v) {
-              fL[v] = (double)trL[NF * M + v];
-              fR[v] = (double)trR[NF * M + v];
-            }
-          } else {
-            PDE::template flux<I>(qL, fL, p.g, pL);
-            PDE::template flux<I>(qR, fR, p.g, pR);
+          if constexpr (K::NQ == 1) {
+            PDE::template flux<I>(qL[r], fL[r], p.g, pL);
+            PDE::template flux<I>(qR[r], fR[r], p.g, pR);
           }
-          l = fmax(PDE::template speed<I>(qL, p.g, pL), PDE::template speed<I>(qR, p.g, pR));
+          l = fmax(PDE::template speed<I>(qL[r], p.g, pL), PDE::template speed<I>(qR[r], p.g, pR));
         }
       });
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        fh[r][v] = 0.5 * (fL[v] + fR[v]);
-        dq[r][v] = qR[v] - qL[v];
+        fh[r][v] = 0.5 * (fL[r][v] + fR[r][v]);
+        dq[r][v] = qR[r][v] - qL[r][v];
       }
       if (!(l >= 0.0)) bad |= 2;      // a trace without a real wave speed (fmax would skip it)
       lam[task] = l;
@@ -652,13 +674,13 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int v = 0; v < M; ++v) Qn[v] = 1.0;
   if (live && t < NS) {
     const int a = t;
-    const double* Qp = p.Qin + (cell * NS + a) * M;
+    if constexpr (!EARLY_Q) {
+      const double* Qp = p.Qin + (cell * NS + a) * M;
 #pragma unroll
-    for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
+      for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
+    }
     static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
       const int k = coord<n, I>(a);
