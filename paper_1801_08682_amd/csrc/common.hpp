@@ -52,6 +52,12 @@ struct KTab {
   double w[n];      // GL weights (time averages)
   double Kv[n][n];  // volume operator
   double FL[n], FR[n], LL[n], LR[n];
+  // Even/odd split of D, which is centro-antisymmetric on the symmetric
+  // Gauss-Legendre nodes (D[n-1-k][n-1-j] = -D[k][j]); for k, j < n/2:
+  // Ce = (D[k][j] + D[k][n-1-j]) / 2, Co = (D[k][j] - D[k][n-1-j]) / 2, and for
+  // odd n the middle column Cm[k] = D[k][n/2] and middle row Dm[j] = D[n/2][j].
+  static constexpr int H = n / 2 > 0 ? n / 2 : 1;
+  Real Ce[H][H], Co[H][H], Cm[H], Dm[H];
 };
 
 template <int n, class Real>
@@ -72,7 +78,86 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
     }
     t.Ps[a] = (Real)ps;
   }
+  for (int k = 0; k < n / 2; ++k) {
+    for (int j = 0; j < n / 2; ++j) {
+      t.Ce[k][j] = (Real)(0.5 * (h.D[k * n + j] + h.D[k * n + (n - 1 - j)]));
+      t.Co[k][j] = (Real)(0.5 * (h.D[k * n + j] - h.D[k * n + (n - 1 - j)]));
+    }
+    t.Cm[k] = (Real)h.D[k * n + n / 2];
+    t.Dm[k] = (Real)h.D[(n / 2) * n + k];
+  }
   return t;
+}
+
+// One pencil's contraction out[k][v] = sum_j D[k][j] F_j[v], F_j from
+// flux_at(j, F).  For n >= 5 the even/odd split needs (n/2)(n/2 + 1) + n/2
+// FMAs per variable for the first half of the rows plus 2 n/2 sums and
+// differences each way, instead of n^2: with E_j = F_j + F_{n-1-j} and
+// O_j = F_j - F_{n-1-j} (j < n/2),
+//   out[k] = S_k + A_k, out[n-1-k] = A_k - S_k, out[n/2] = sum_j Dm[j] O_j,
+//   S_k = sum_j Ce[k][j] E_j + Cm[k] F_{n/2} (odd n), A_k = sum_j Co[k][j] O_j.
+template <int n, int M, class Real, class Tab, class FluxAt>
+__device__ __forceinline__ void pencil_dF(const Tab& t, FluxAt&& flux_at, Real (&out)[n][M]) {
+  if constexpr (n < 5) {
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int v = 0; v < M; ++v) out[k][v] = Real(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      Real F[M];
+      flux_at(j, F);
+#pragma unroll
+      for (int k = 0; k < n; ++k)
+#pragma unroll
+        for (int v = 0; v < M; ++v) out[k][v] = fma(t.D[k][j], F[v], out[k][v]);
+    }
+  } else {
+    constexpr int h = n / 2;
+    constexpr bool odd = (n % 2) == 1;
+    Real S[h][M], A[h][M], Mid[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      Mid[v] = Real(0);
+#pragma unroll
+      for (int k = 0; k < h; ++k) S[k][v] = A[k][v] = Real(0);
+    }
+#pragma unroll
+    for (int j = 0; j < h; ++j) {
+      Real Fa[M], Fb[M];
+      flux_at(j, Fa);
+      flux_at(n - 1 - j, Fb);
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        const Real E = Fa[v] + Fb[v], O = Fa[v] - Fb[v];
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+          S[k][v] = fma(t.Ce[k][j], E, S[k][v]);
+          A[k][v] = fma(t.Co[k][j], O, A[k][v]);
+        }
+        if constexpr (odd) Mid[v] = fma(t.Dm[j], O, Mid[v]);
+      }
+    }
+    if constexpr (odd) {
+      Real Fm[M];
+      flux_at(h, Fm);
+#pragma unroll
+      for (int k = 0; k < h; ++k)
+#pragma unroll
+        for (int v = 0; v < M; ++v) S[k][v] = fma(t.Cm[k], Fm[v], S[k][v]);
+    }
+#pragma unroll
+    for (int k = 0; k < h; ++k)
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        out[k][v] = S[k][v] + A[k][v];
+        out[n - 1 - k][v] = A[k][v] - S[k][v];
+      }
+    if constexpr (odd) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) out[h][v] = Mid[v];
+    }
+  }
 }
 
 // Everything a launcher needs from the context.

@@ -57,6 +57,10 @@ struct Fwd {
   __device__ static __forceinline__ int lidx(int tt, int v, int pos);
   // Lanes the LDS serves per cycle for this layout's accesses: 16-byte words
   // 16 lanes, 8-byte words 32 lanes, 4-byte words 64 lanes (64 banks of 4 B).
+  // Axis sums of a pencil (n m values): all reads before the writes, except
+  // for large float pencils, where the extra live values cost more waves
+  // than the serialised node-by-node read-modify-write.
+  static constexpr bool READ_FIRST = PAIRS || n * M <= 32;
   static constexpr int NGROUP = PAIRS ? 2 : 1;
   static constexpr int group(int c) { return PAIRS ? (c == 0 ? 16 : 32) : 64; }
   static constexpr int LDS_BUDGET = 80 * 1024;
@@ -223,25 +227,16 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       constexpr int sI = ipow(n, I);
       auto pencil = [&](int e0) {
         Real out[n][M];
+        pencil_dF<n, M, Real>(p.t, [&](int j, Real (&F)[M]) {
+          Real qn[M];
 #pragma unroll
-        for (int k = 0; k < n; ++k)
-#pragma unroll
-          for (int v = 0; v < M; ++v) out[k][v] = Real(0);
-#pragma unroll
-        for (int j = 0; j < n; ++j) {
-          const int e = e0 + j * sI;
-          Real qn[M], F[M];
-#pragma unroll
-          for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e, v)];
+          for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e0 + j * sI, v)];
           PDE::template flux_pub<I>(qn, F, p.g, cp);
-#pragma unroll
-          for (int k = 0; k < n; ++k)
-#pragma unroll
-            for (int v = 0; v < M; ++v) out[k][v] = fma(p.t.D[k][j], F[v], out[k][v]);
-        }
-        // axis sums: every read of the pencil before any write, so the reads
-        // are not serialised behind possibly aliasing stores
-        if constexpr (I > 0) {
+        }, out);
+        // axis sums: for small pencils every read before any write, so the
+        // reads are not serialised behind possibly aliasing stores; large
+        // ones node by node (fewer live registers)
+        if constexpr (I > 0 && K::READ_FIRST) {
 #pragma unroll
           for (int k = 0; k < n; ++k)
 #pragma unroll
@@ -250,7 +245,10 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
 #pragma unroll
         for (int k = 0; k < n; ++k)
 #pragma unroll
-          for (int v = 0; v < M; ++v) Rs[K::template lidx_e<S>(e0 + k * sI, v)] = out[k][v];
+          for (int v = 0; v < M; ++v) {
+            if constexpr (I > 0 && !K::READ_FIRST) out[k][v] += Rs[K::template lidx_e<S>(e0 + k * sI, v)];
+            Rs[K::template lidx_e<S>(e0 + k * sI, v)] = out[k][v];
+          }
       };
       if (ns * NF == NS || a < ns * NF) pencil(e0_of(NS_, I_));   // at most one task per thread
       __syncthreads();
@@ -310,23 +308,13 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         constexpr int I = decltype(I_)::value;
         constexpr int sI = ipow(n, I);
         const int e0 = e0_of(NS_, I_);
-#pragma unroll
-        for (int k = 0; k < n; ++k)
-#pragma unroll
-          for (int v = 0; v < M; ++v) out[I][k][v] = Real(0);
         if (act) {
+          pencil_dF<n, M, Real>(p.t, [&](int j, Real (&F)[M]) {
+            Real qn[M];
 #pragma unroll
-          for (int j = 0; j < n; ++j) {
-            const int e = e0 + j * sI;
-            Real qn[M], F[M];
-#pragma unroll
-            for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e, v)];
+            for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e0 + j * sI, v)];
             PDE::template flux_pub<I>(qn, F, p.g, cp);
-#pragma unroll
-            for (int k = 0; k < n; ++k)
-#pragma unroll
-              for (int v = 0; v < M; ++v) out[I][k][v] = fma(p.t.D[k][j], F[v], out[I][k][v]);
-          }
+          }, out[I]);
         }
       });
       __syncthreads();                              // all pencils read: reuse Qs as rhs
@@ -335,8 +323,8 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         if (act) {
           constexpr int sI = ipow(n, I);
           const int e0 = e0_of(NS_, I_);
-          // every read of the pencil before any write (see contract)
-          if constexpr (I > 0) {
+          // small pencils: every read before any write (see contract)
+          if constexpr (I > 0 && K::READ_FIRST) {
 #pragma unroll
             for (int k = 0; k < n; ++k)
 #pragma unroll
@@ -345,7 +333,10 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
 #pragma unroll
           for (int k = 0; k < n; ++k)
 #pragma unroll
-            for (int v = 0; v < M; ++v) Qs[K::template lidx_e<S>(e0 + k * sI, v)] = out[I][k][v];
+            for (int v = 0; v < M; ++v) {
+              if constexpr (I > 0 && !K::READ_FIRST) out[I][k][v] += Qs[K::template lidx_e<S>(e0 + k * sI, v)];
+              Qs[K::template lidx_e<S>(e0 + k * sI, v)] = out[I][k][v];
+            }
         }
         __syncthreads();
       });
