@@ -227,6 +227,32 @@ def run_path(st, Q0, steps, warmup, cfl, torch):
     return Q, wall, pred, corr, dtk
 
 
+def spacetime_workload(args, torch):
+    """The headline workload with space-time traces (Table 1's cardinalities:
+    q and F.n at every time node of every face node, a Rusanov solve per
+    time node): float64, fused and two-kernel paths, and the measured HBM
+    bytes of the corrector and predictor against their algorithmic bytes."""
+    from paper_1801_08682_amd import inputs
+    from paper_1801_08682_amd.stepper import Stepper
+    wl = inputs.preset("C2").with_(n_cells=(args.cells,) * 3, length=args.cells / 81.0)
+    d, n, m = wl.dim, wl.n, wl.m
+    Q0 = torch.tensor(inputs.initial_state(wl), device="cuda")
+    st = Stepper(wl, fused=True, spacetime=True)
+    Q, wall, sweep, reruns, _ = run_fused_path(st, Q0, args.steps, args.warmup, wl.cfl, C_DT, torch)
+    _, wall2, pred, corr, dtk = run_path(st, Q0, args.steps, args.warmup, wl.cfl, torch)
+    st.close()
+    dofs = wl.ncells * wl.dofs_per_cell
+    hull = 2 * d * 2 * m * n ** d * 8                     # bytes per cell, every time node
+    return {"metric": "DoF-updates/s", "unit": "DoF-updates/s",
+            "workload": f"C2 with space-time traces ({args.cells}^3 cells, Euler N=4)",
+            "fused": {"value": dofs * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
+                      "sweep_ms": sweep, "reruns": reruns},
+            "two_kernel": {"value": dofs * args.steps / wall2, "ms_per_step": wall2 * 1e3 / args.steps,
+                           "kernel_ms": {"predict": pred, "correct": corr, "cfl_dt": dtk}},
+            "hull_bytes_per_cell": hull,
+            "correct_hbm_GBps": (2 * m * n ** d * 8 + hull) * wl.ncells / (corr * 1e-3) / 1e9}
+
+
 def run_fused_path(st, Q0, steps, warmup, cfl, c_dt, torch):
     """Alg. 2 stepping: warm-up run on a copy, then adg_fused_begin, `steps`
     - 1 sweeps (each timed with events on the stepper's stream) and
@@ -266,6 +292,9 @@ def main():
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"],
                     help="C2 is the headline line; the others print their own line "
                          "(float64 and float-predictor throughput and per-field error)")
+    ap.add_argument("--traces", default="time-integrated", choices=["time-integrated", "spacetime"],
+                    help="spacetime: print one line for the headline workload with space-time "
+                         "traces and a Rusanov solve per time node")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -280,6 +309,9 @@ def main():
 
     if args.workload != "C2":
         print(json.dumps(other_workload(args, torch)), flush=True)
+        return
+    if args.traces == "spacetime":
+        print(json.dumps(spacetime_workload(args, torch)), flush=True)
         return
     wl = inputs.preset("C2").with_(n_cells=(args.cells,) * 3,
                                    length=args.cells / 81.0)

@@ -75,6 +75,11 @@ typedef struct {
   int32_t precision;      /* adg_precision */
   int32_t adjoint;        /* nonzero: reserve workspace for adg_step_adjoint (FP64 only) */
   int32_t fused;          /* nonzero: reserve workspace for adg_run_fused */
+  int32_t spacetime_traces; /* nonzero: the hull keeps q and F.n at every time node and the
+                               Riemann problems are solved per time node (Table 1's
+                               extrapolate and solveRiemann cardinalities), F* integrated in
+                               time; FP64, orders up to 5, no adjoint.  0: time-integrated
+                               traces (one value per face node) */
 } adg_config;
 
 typedef struct adg_ctx adg_ctx;
@@ -83,8 +88,8 @@ typedef struct adg_ctx adg_ctx;
  *   dofs_per_cell   = m (N+1)^d   (Sec. 3: m (p+1)^d coefficients per cell)
  *   params_per_cell = per-cell material count (0, 1 or 3)
  *   workspace_bytes = device workspace the caller must pass to adg_init: the
- *                     time-integrated face hull (Theorem 1; Table 1 task
- *                     extrapolate, reduced to one time value per face node)
+ *                     face hull (Theorem 1; Table 1 task extrapolate: one time
+ *                     value per face node, or N+1 with cfg->spacetime_traces)
  *                     plus reduction scratch; with cfg->adjoint also a copy
  *                     of Q, the hull's bars and per-block Picard scratch
  *                     (at most 2048 blocks, at most 2 GiB); with cfg->fused a

@@ -30,7 +30,8 @@ class AdgConfig(ctypes.Structure):
                 ("picard_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32),
-                ("fused", ctypes.c_int32)]
+                ("fused", ctypes.c_int32),
+                ("spacetime_traces", ctypes.c_int32)]
 
 
 class AdgError(RuntimeError):
@@ -90,7 +91,7 @@ def check(status, ctx=None):
 
 
 def make_config(dim, order, n_cells, length, pde, pde_param=(), picard_iters=0, precision=0,
-                adjoint=False, fused=False):
+                adjoint=False, fused=False, spacetime=False):
     c = AdgConfig()
     c.dim = dim
     c.order = order
@@ -108,6 +109,7 @@ def make_config(dim, order, n_cells, length, pde, pde_param=(), picard_iters=0, 
     c.precision = precision
     c.adjoint = 1 if adjoint else 0
     c.fused = 1 if fused else 0
+    c.spacetime_traces = 1 if spacetime else 0
     return c
 
 

@@ -85,10 +85,10 @@ adg_status validate(const adg_config* c, std::string* msg) {
 
 const adg::Launchers* find(const adg_config* c) {
   switch (c->pde) {
-    case ADG_ADVECTION: return adg::find_advection(c->dim, c->order, c->precision);
-    case ADG_EULER: return adg::find_euler(c->dim, c->order, c->precision);
-    case ADG_ACOUSTIC: return adg::find_acoustic(c->dim, c->order, c->precision);
-    case ADG_ELASTIC: return adg::find_elastic(c->dim, c->order, c->precision);
+    case ADG_ADVECTION: return adg::find_advection(c->dim, c->order, c->precision, c->spacetime_traces != 0);
+    case ADG_EULER: return adg::find_euler(c->dim, c->order, c->precision, c->spacetime_traces != 0);
+    case ADG_ACOUSTIC: return adg::find_acoustic(c->dim, c->order, c->precision, c->spacetime_traces != 0);
+    case ADG_ELASTIC: return adg::find_elastic(c->dim, c->order, c->precision, c->spacetime_traces != 0);
   }
   return nullptr;
 }

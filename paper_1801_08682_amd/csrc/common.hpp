@@ -209,10 +209,10 @@ struct Launchers {
 };
 
 // Registries implemented by the per-PDE instantiation units.
-const Launchers* find_advection(int dim, int order, int prec);
-const Launchers* find_euler(int dim, int order, int prec);
-const Launchers* find_acoustic(int dim, int order, int prec);
-const Launchers* find_elastic(int dim, int order, int prec);
+const Launchers* find_advection(int dim, int order, int prec, bool st);
+const Launchers* find_euler(int dim, int order, int prec, bool st);
+const Launchers* find_acoustic(int dim, int order, int prec, bool st);
+const Launchers* find_elastic(int dim, int order, int prec, bool st);
 
 // Grid size used by every cell-parallel reduction kernel (partial maxima).
 constexpr int64_t kMaxReduceBlocks = 16384;

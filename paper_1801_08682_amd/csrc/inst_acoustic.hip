@@ -3,9 +3,9 @@
 
 namespace adg {
 
-const Launchers* find_acoustic(int dim, int order, int prec) {
-  if (dim == 2) return pick_order<Acoustic, 2, 1, 2, 3, 4>(order, prec);
-  if (dim == 3) return pick_order<Acoustic, 3, 1, 2, 3, 4, 5>(order, prec);
+const Launchers* find_acoustic(int dim, int order, int prec, bool st) {
+  if (dim == 2) return pick_order<Acoustic, 2, 1, 2, 3, 4>(order, prec, st);
+  if (dim == 3) return pick_order<Acoustic, 3, 1, 2, 3, 4, 5>(order, prec, st);
   return nullptr;
 }
 

@@ -3,9 +3,9 @@
 
 namespace adg {
 
-const Launchers* find_euler(int dim, int order, int prec) {
-  if (dim == 2) return pick_order<Euler, 2, 0, 1, 2, 3, 4, 5>(order, prec);
-  if (dim == 3) return pick_order<Euler, 3, 0, 1, 2, 3, 4, 5, 7>(order, prec);
+const Launchers* find_euler(int dim, int order, int prec, bool st) {
+  if (dim == 2) return pick_order<Euler, 2, 0, 1, 2, 3, 4, 5>(order, prec, st);
+  if (dim == 3) return pick_order<Euler, 3, 0, 1, 2, 3, 4, 5, 7>(order, prec, st);
   return nullptr;
 }
 

@@ -23,9 +23,14 @@
 
 namespace adg {
 
-template <int D_, int N_, template <int> class PDET, class Real_>
+// ST_: the hull keeps the traces at every time node (Table 1's extrapolate
+// cardinality) and the Riemann problems are solved per time node; otherwise
+// the traces are time-integrated (one time value per face node).
+template <int D_, int N_, template <int> class PDET, class Real_, bool ST_ = false>
 struct Fwd {
   static constexpr int D = D_, N = N_, n = N_ + 1;
+  static constexpr bool ST = ST_;
+  static constexpr int NT = ST_ ? N_ + 1 : 1;         // time values per trace
   using PDE = PDET<D_>;
   using Real = Real_;
   static constexpr int M = PDE::M, NPAR = PDE::NPAR;
@@ -80,21 +85,24 @@ struct Fwd {
   static constexpr int PIC_BYTES = (ALIAS ? 1 : 2) * S * NSP * MP * (int)sizeof(Real);
   static constexpr int FIRST_BYTES = D * NSP * MP * (int)sizeof(Real);   // d flux planes of u
   static constexpr int FIN_BYTES = (D + 2) * NS * M * 8;                 // Fbar_i, qbar, V
+                                                                          // (or q, F_i at one time node)
   static constexpr int max3(int x, int y, int z) { return x > y ? (x > z ? x : z) : (y > z ? y : z); }
   static constexpr int CELL_BYTES = (max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
-  static constexpr int64_t TRACE_ELEMS = 2LL * D * NQ * NF * M;   // per cell
+  // per cell; layout [face][time][qty][face node][var]
+  static constexpr int64_t TRACE_ELEMS = 2LL * D * NT * NQ * NF * M;
+  static constexpr int64_t TFACE = (int64_t)NT * NQ * NF * M;   // one face
   // corrector block: one thread per face task and per node
   static constexpr int FT = 2 * D * NF;
   static constexpr int CT = NS > FT ? NS : FT;
   static constexpr int CCPB = (CT >= 128) ? 1 : 128 / CT;
   static constexpr int CTHREADS = CCPB * CT;
-  static constexpr int CORR_CELL_BYTES = (2 * D * NF * (M + 1) + 2 * D) * 8;
+  static constexpr int CORR_CELL_BYTES = (2 * D * NF * (M + NT) + 2 * D * NT) * 8;
 };
 
-template <int D_, int N_, template <int> class PDET, class Real_>
-__device__ __forceinline__ int Fwd<D_, N_, PDET, Real_>::lidx(int tt, int v, int pos) {
+template <int D_, int N_, template <int> class PDET, class Real_, bool ST_>
+__device__ __forceinline__ int Fwd<D_, N_, PDET, Real_, ST_>::lidx(int tt, int v, int pos) {
   return lidx_e<S>(tt * NSP + pos, v);
 }
 
@@ -462,10 +470,10 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       }
 #pragma unroll
       for (int k = 0; k < n; ++k) Vs[v * NS + pencil_node<n, I>(b, k)] = vol[k];
-      if (live) {
+      if (!K::ST && live) {
         Real* tr = p.tr + cs * K::TRACE_ELEMS + b * M + v;
-        Real* tL = tr + (int64_t)(2 * I) * K::NQ * NF * M;
-        Real* tR = tr + (int64_t)(2 * I + 1) * K::NQ * NF * M;
+        Real* tL = tr + (int64_t)(2 * I) * K::TFACE;
+        Real* tR = tr + (int64_t)(2 * I + 1) * K::TFACE;
         tL[0] = (Real)qL;
         tR[0] = (Real)qR;
         if constexpr (K::NQ == 2) {
@@ -479,6 +487,56 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   if (live) {
 #pragma unroll
     for (int v = 0; v < M; ++v) p.Qout[(cell * NS + a) * M + v] = u[v] + cdt * Vs[v * NS + a];
+  }
+  if constexpr (K::ST) {
+    // ---- extrapolate at every time node (Table 1): q(t) and F_i(q(t)) ----
+    double* Ts = reinterpret_cast<double*>(base);   // [slot: q, F_0 .. F_{d-1}][var][node]
+    static_for<0, n>([&](auto T_) {
+      constexpr int t = decltype(T_)::value;
+      __syncthreads();                               // Vs / the last slice read
+#pragma unroll
+      for (int v = 0; v < M; ++v) Ts[v * NS + a] = (double)q[t][v];
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        if constexpr (K::NQ == 2) {
+          Real F[M];
+          PDE::template flux<I>(q[t], F, p.g, cp);
+#pragma unroll
+          for (int v = 0; v < M; ++v) Ts[((1 + I) * M + v) * NS + a] = (double)F[v];
+        }
+      });
+      __syncthreads();
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        for (int task = a; task < M * NF; task += NS) {
+          const int v = task / NF, b = task - v * NF;
+          double qL = 0.0, qR = 0.0, fL = 0.0, fR = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            const int nd = pencil_node<n, I>(b, j);
+            const double qv = Ts[v * NS + nd];
+            qL += p.t.FL[j] * qv;
+            qR += p.t.FR[j] * qv;
+            if constexpr (K::NQ == 2) {
+              const double fv = Ts[((1 + I) * M + v) * NS + nd];
+              fL += p.t.FL[j] * fv;
+              fR += p.t.FR[j] * fv;
+            }
+          }
+          if (live) {
+            Real* tr = p.tr + cs * K::TRACE_ELEMS + (int64_t)t * K::NQ * NF * M + b * M + v;
+            Real* tL = tr + (int64_t)(2 * I) * K::TFACE;
+            Real* tR = tr + (int64_t)(2 * I + 1) * K::TFACE;
+            tL[0] = (Real)qL;
+            tR[0] = (Real)qR;
+            if constexpr (K::NQ == 2) {
+              tL[NF * M] = (Real)fL;
+              tR[NF * M] = (Real)fR;
+            }
+          }
+        }
+      });
+    });
   }
 }
 
@@ -531,6 +589,7 @@ struct CorrP {
   double inv_h;
   Gconst<double> g;
   double LL[K::n], LR[K::n];
+  double w[K::n];        // Gauss-Legendre weights (time integral of space-time fluxes)
 };
 
 // Cell visited at position g of a brick-major walk of the grid (bricks of
@@ -570,27 +629,125 @@ __device__ __forceinline__ int64_t neighbour(int64_t cell, int i, int dir, const
 // state of node t in Qn, its largest directional speed folded into lmax and
 // the admissibility flags into bad (2 also for a face trace whose wave speed
 // is not a real number).  lds: the cell's K::CORR_CELL_BYTES.
-template <class K, int NT>
+template <class K, int NTH>
 __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t, int64_t cell,
                                           bool live, double (&Qn)[K::M], double& lmax, int& bad) {
   using Real = typename K::Real;
   using PDE = typename K::PDE;
   constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, FT = K::FT;
-  constexpr int TPT = (FT + NT - 1) / NT;                 // face tasks per thread
-  double* lam = lds;                                     // [2D][NF]
-  double* Fs = lam + 2 * D * NF;                         // [2D][NF][M]
-  double* sm = Fs + 2 * D * NF * M;                      // [2D]
+  constexpr int TPT = (FT + NTH - 1) / NTH;               // face tasks per thread
+  constexpr bool EARLY_Q = TPT > 1;                       // see the time-integrated branch
+  double* lam = lds;                                     // [2D][NT][NF]
+  double* Fs = lam + 2 * D * NF * K::NT;                 // [2D][NF][M]
+  double* sm = Fs + 2 * D * NF * M;                      // [2D][NT]
   const double cdt = (*p.dt) * p.inv_h;
+  if constexpr (K::ST) {
+    // Space-time traces, in two passes over the time nodes of every face task
+    // (the second one finds the traces in L2): the speeds give one s per face
+    // and time node; then F* is integrated in time, sum_t w_t F*(t).
+#pragma unroll
+    for (int v = 0; v < M; ++v) Qn[v] = 1.0;
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+      const int task = t + r * NTH;
+      if (live && task < FT) {
+        const int f = task / NF, b = task - f * NF;
+        const int i = f >> 1, s = f & 1;
+        const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
+        const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
+        const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
+        const auto pR = PDE::template cell<double>(p.par + cR * K::NPAR);
+#pragma unroll 1
+        for (int tt = 0; tt < K::NT; ++tt) {
+          const int64_t off = (int64_t)tt * K::NQ * NF * M + b * M;
+          const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + off;
+          const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + off;
+          double qL[M], qR[M];
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            qL[v] = (double)trL[v];
+            qR[v] = (double)trR[v];
+          }
+          double l = 0.0;
+          static_for<0, D>([&](auto I_) {
+            constexpr int I = decltype(I_)::value;
+            if (i == I) l = fmax(PDE::template speed<I>(qL, p.g, pL), PDE::template speed<I>(qR, p.g, pR));
+          });
+          if (!(l >= 0.0)) bad |= 2;
+          lam[(f * K::NT + tt) * NF + b] = l;
+        }
+      }
+    }
+    __syncthreads();
+    for (int ft = t; ft < 2 * D * K::NT; ft += NTH) {
+      if (live) {
+        double sv = 0.0;
+        for (int b = 0; b < NF; ++b) sv = fmax(sv, lam[ft * NF + b]);
+        sm[ft] = sv;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+      const int task = t + r * NTH;
+      if (live && task < FT) {
+        const int f = task / NF, b = task - f * NF;
+        const int i = f >> 1, s = f & 1;
+        const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
+        const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
+        const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
+        const auto pR = PDE::template cell<double>(p.par + cR * K::NPAR);
+        double acc[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) acc[v] = 0.0;
+#pragma unroll 1
+        for (int tt = 0; tt < K::NT; ++tt) {
+          const int64_t off = (int64_t)tt * K::NQ * NF * M + b * M;
+          const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + off;
+          const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + off;
+          double qL[M], qR[M], fL[M], fR[M];
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            qL[v] = (double)trL[v];
+            qR[v] = (double)trR[v];
+            if constexpr (K::NQ == 2) {
+              fL[v] = (double)trL[NF * M + v];
+              fR[v] = (double)trR[NF * M + v];
+            }
+          }
+          if constexpr (K::NQ == 1) {
+            static_for<0, D>([&](auto I_) {
+              constexpr int I = decltype(I_)::value;
+              if (i == I) {
+                PDE::template flux<I>(qL, fL, p.g, pL);
+                PDE::template flux<I>(qR, fR, p.g, pR);
+              }
+            });
+          }
+          const double hw = 0.5 * p.w[tt], hs = hw * sm[f * K::NT + tt];
+#pragma unroll
+          for (int v = 0; v < M; ++v) acc[v] += hw * (fL[v] + fR[v]) - hs * (qR[v] - qL[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fs[task * M + v] = acc[v];
+      }
+    }
+    __syncthreads();
+    if (live && t < NS) {
+      const double* Qp = p.Qin + (cell * NS + t) * M;
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
+    }
+  } else {
   // Every load of the cell first (the face traces of all of this thread's
   // tasks and, with several tasks per thread, the node's Q~), so that their
-  // latencies overlap.  With one task per thread (NT >= FT) the Q~ load
+  // latencies overlap.  With one task per thread (NTH >= FT) the Q~ load
   // waits for the update: fewer live registers, more waves for k_corr.
-  constexpr bool EARLY_Q = TPT > 1;
   double qL[TPT][M], qR[TPT][M], fL[TPT][M], fR[TPT][M];
   int64_t cLr[TPT], cRr[TPT];
 #pragma unroll
   for (int r = 0; r < TPT; ++r) {
-    const int task = t + r * NT;
+    const int task = t + r * NTH;
     cLr[r] = cRr[r] = 0;
     if (live && task < FT) {
       const int f = task / NF, b = task - f * NF;
@@ -622,7 +779,7 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
   double fh[TPT][M], dq[TPT][M];
 #pragma unroll
   for (int r = 0; r < TPT; ++r) {
-    const int task = t + r * NT;
+    const int task = t + r * NTH;
     if (live && task < FT) {
       const int f = task / NF;
       const int i = f >> 1;
@@ -657,7 +814,7 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < TPT; ++r) {
-    const int task = t + r * NT;
+    const int task = t + r * NTH;
     if (live && task < FT) {
       const double hs = 0.5 * sm[task / NF];
 #pragma unroll
@@ -665,9 +822,10 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
     }
   }
   __syncthreads();
+  }
   if (live && t < NS) {
     const int a = t;
-    if constexpr (!EARLY_Q) {
+    if constexpr (!K::ST && !EARLY_Q) {
       const double* Qp = p.Qin + (cell * NS + a) * M;
 #pragma unroll
       for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
@@ -860,6 +1018,7 @@ CorrP<K> corr_params(const LaunchArgs& a) {
   for (int k = 0; k < K::n; ++k) {
     p.LL[k] = a.tab->LL[k];
     p.LR[k] = a.tab->LR[k];
+    p.w[k] = a.tab->w[k];
   }
   for (int k = 0; k < 3; ++k) p.brick[k] = a.brick[k];
   return p;

@@ -1,5 +1,5 @@
-// Compile-time registry: which (dim, order, precision) combinations of a PDE
-// are instantiated.  Included by exactly one instantiation unit per PDE.
+// Compile-time registry: which (dim, order, precision, trace kind)
+// combinations of a PDE are instantiated.  Included by exactly one instantiation unit per PDE.
 #pragma once
 
 #include "kernels_adj.hpp"
@@ -7,7 +7,16 @@
 namespace adg {
 
 template <template <int> class PDET, int D, int N>
-const Launchers* pick_precision(int prec) {
+const Launchers* pick_precision(int prec, bool st) {
+  if (st) {     // space-time traces: float64, orders up to 5
+    if constexpr (N <= 5) {
+      if (prec == 0) {
+        static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, double, true>>();
+        return &L;
+      }
+    }
+    return nullptr;
+  }
   if (prec == 0) {
     using K = Fwd<D, N, PDET, double>;
     static const Launchers L = [] {
@@ -26,9 +35,9 @@ const Launchers* pick_precision(int prec) {
 }
 
 template <template <int> class PDET, int D, int... Ns>
-const Launchers* pick_order(int order, int prec) {
+const Launchers* pick_order(int order, int prec, bool st) {
   const Launchers* r = nullptr;
-  ((order == Ns ? (r = pick_precision<PDET, D, Ns>(prec), 0) : 0), ...);
+  ((order == Ns ? (r = pick_precision<PDET, D, Ns>(prec, st), 0) : 0), ...);
   return r;
 }
 

@@ -24,7 +24,8 @@ class Stepper:
     params: (ncells, npar) float64 or None.  dt: float64 device tensor (1,).
     """
 
-    def __init__(self, wl: Workload, device="cuda", stream=None, adjoint=False, fused=False):
+    def __init__(self, wl: Workload, device="cuda", stream=None, adjoint=False, fused=False,
+                 spacetime=False):
         self.wl = wl
         self.L = _lib.load()
         self.device = torch.device(device)
@@ -32,7 +33,7 @@ class Stepper:
                                     [wl.length * wl.n_cells[i] / wl.n_cells[0]
                                      for i in range(wl.dim)],
                                     wl.pde, wl.pde_param, wl.picard_iters, wl.precision,
-                                    adjoint, fused)
+                                    adjoint, fused, spacetime)
         self.dofs_per_cell, self.npar, self.ws_bytes = _lib.query(self.cfg)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.stream(self.stream):

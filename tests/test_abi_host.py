@@ -154,3 +154,23 @@ def test_query_fused_workspace(L, name):
     nq = 2 if wl.pde == inputs.EULER else 1
     extra = wl.ncells * m * n ** d * 8 + wl.ncells * 2 * d * nq * m * n ** (d - 1) * 8 + 256
     assert extra <= wf - w <= extra + 2 * 256
+
+
+def test_query_spacetime_traces(L):
+    """Space-time traces keep N+1 time values per face node (Table 1's
+    extrapolate output, 4 d m (N+1)^d per cell for Euler); float64 and orders
+    up to 5 only."""
+    wl = inputs.preset("C2")
+    _, _, w = _lib.query(cfg_of(wl))
+    c = cfg_of(wl)
+    c.spacetime_traces = 1
+    _, _, ws = _lib.query(c)
+    n, d, m = wl.n, wl.dim, wl.m
+    hull = wl.ncells * 4 * d * m * n ** (d - 1) * 8
+    assert wl.ncells * 4 * d * m * n ** d * 8 == n * hull
+    assert abs((ws - w) - (n - 1) * hull) <= 2 * 256
+    c.precision = inputs.FP32
+    assert L.adg_query(ctypes.byref(c), None, None, None) == _lib.ADG_ERR_UNSUPPORTED
+    c = cfg_of(inputs.preset("C5"))
+    c.spacetime_traces = 1
+    assert L.adg_query(ctypes.byref(c), None, None, None) == _lib.ADG_ERR_UNSUPPORTED
