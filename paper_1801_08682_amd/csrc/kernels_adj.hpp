@@ -206,7 +206,7 @@ constexpr int64_t adj_slot_doubles(int R) {
 // LDS index in a buffer of S time slices (the forward predictor's layout).
 template <class K, int S>
 __device__ __forceinline__ int alidx(int tt, int v, int pos) {
-  return K::template lidx_e<S>(tt * K::NSP + pos, v);
+  return K::template lidx_e<S>(tt * K::NSP + K::slot(pos), v);
 }
 
 // One thread per spatial node, CPB cells per workgroup, one cell per thread
@@ -226,7 +226,8 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
   constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, NPAR = K::NPAR;
   constexpr int CPB = K::CPB, S = Plan::S;
   __shared__ __align__(16) double smem[CPB * Plan::CELL];
-  __shared__ double pred[NPAR > 0 ? CPB * NPAR * NS : 1];
+  static_assert(NPAR * NS <= Plan::CELL, "material bars reuse the slice buffers");
+  double* pred = smem;                         // material-bar reduction, after the sweep
   const int lc = threadIdx.x / NS;
   const int a = threadIdx.x - lc * NS;
   double* A = smem + lc * Plan::CELL;          // published slices
@@ -250,42 +251,35 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
 #pragma unroll
     for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
 
-    // Forward pencils: B <- sum_i D_i F_i(A) on ns slices.
+    // Forward pencils: B <- sum_i D_i F_i(A) on ns slices.  Lanes take the
+    // pencil tasks in the forward predictor's bank-conflict-free order; a
+    // task is its first slot e0 (slice and pencil base), then stride sI.
     auto fwd_contract = [&](auto NS_) {
       constexpr int ns = decltype(NS_)::value;
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
+        constexpr int sI = K::sstride(I);
         if (a < ns * NF) {
-          const int tt = a / NF, b = a - tt * NF;
+          const int e0 = task_e0<K, ns, I>(a);
           double out[n][M];
+          pencil_dF<n, M, double>(p.t, [&](int j, double (&F)[M]) {
+            double qn[M];
 #pragma unroll
-          for (int k = 0; k < n; ++k)
-#pragma unroll
-            for (int v = 0; v < M; ++v) out[k][v] = 0.0;
-#pragma unroll
-          for (int j = 0; j < n; ++j) {
-            const int nd = pencil_node<n, I>(b, j);
-            double qn[M], F[M];
-#pragma unroll
-            for (int v = 0; v < M; ++v) qn[v] = A[alidx<K, S>(tt, v, nd)];
+            for (int v = 0; v < M; ++v) qn[v] = A[K::template lidx_e<S>(e0 + j * sI, v)];
             PDE::template flux<I>(qn, F, p.g, cp);
-#pragma unroll
-            for (int k = 0; k < n; ++k)
-#pragma unroll
-              for (int v = 0; v < M; ++v) out[k][v] = fma(p.t.D[k][j], F[v], out[k][v]);
-          }
+          }, out);
           // every read of the pencil before any write: no serialised
           // read-modify-write through possibly aliasing stores
           if constexpr (I > 0) {
 #pragma unroll
             for (int k = 0; k < n; ++k)
 #pragma unroll
-              for (int v = 0; v < M; ++v) out[k][v] += B[alidx<K, S>(tt, v, pencil_node<n, I>(b, k))];
+              for (int v = 0; v < M; ++v) out[k][v] += B[K::template lidx_e<S>(e0 + k * sI, v)];
           }
 #pragma unroll
           for (int k = 0; k < n; ++k)
 #pragma unroll
-            for (int v = 0; v < M; ++v) B[alidx<K, S>(tt, v, pencil_node<n, I>(b, k))] = out[k][v];
+            for (int v = 0; v < M; ++v) B[K::template lidx_e<S>(e0 + k * sI, v)] = out[k][v];
         }
         __syncthreads();
       });
@@ -293,24 +287,22 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
     // Reverse pencils of axis I: B <- D_I^T A on ns slices.
     auto rev_contract = [&](auto NS_, auto I_) {
       constexpr int ns = decltype(NS_)::value, I = decltype(I_)::value;
+      constexpr int sI = K::sstride(I);
       if (a < ns * NF) {
-        const int tt = a / NF, b = a - tt * NF;
+        const int e0 = task_e0<K, ns, I>(a);
         double in[n][M];
 #pragma unroll
-        for (int j = 0; j < n; ++j) {
-          const int nd = pencil_node<n, I>(b, j);
+        for (int j = 0; j < n; ++j)
 #pragma unroll
-          for (int v = 0; v < M; ++v) in[j][v] = A[alidx<K, S>(tt, v, nd)];
-        }
+          for (int v = 0; v < M; ++v) in[j][v] = A[K::template lidx_e<S>(e0 + j * sI, v)];
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-          const int nd = pencil_node<n, I>(b, k);
 #pragma unroll
           for (int v = 0; v < M; ++v) {
-            double s = 0.0;
+            double acc = 0.0;
 #pragma unroll
-            for (int j = 0; j < n; ++j) s = fma(p.t.D[j][k], in[j][v], s);
-            B[alidx<K, S>(tt, v, nd)] = s;
+            for (int j = 0; j < n; ++j) acc = fma(p.t.D[j][k], in[j][v], acc);
+            B[K::template lidx_e<S>(e0 + k * sI, v)] = acc;
           }
         }
       }

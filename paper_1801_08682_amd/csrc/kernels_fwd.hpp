@@ -47,7 +47,16 @@ struct Fwd {
   // by 3.  The pencil tasks are dealt to the lanes in the order of
   // TaskOrder below, which keeps every access free of bank conflicts.
   static constexpr bool PAIRS = std::is_same<Real, double>::value;
-  static constexpr int NSP = NS + (PAIRS ? 0 : 3);
+  // Slots of a slice: node (x, rest) sits at slot x + XP * rest.  When n is a
+  // multiple of 4 every x-row is padded to n + 1 slots: the pencils along x
+  // then start n + 1 slots apart, an odd stride, where n apart would put
+  // gcd(n, 16) lanes of a 16-lane access on one bank (4-way at n = 4, 8-way
+  // at n = 8; the 2-way case n = 6 is cheaper than the padding).
+  static constexpr int XP = (n % 4 == 0) ? n + 1 : n;
+  static constexpr int NSLOT = XP * NF;
+  __host__ __device__ static constexpr int slot(int node) { return (node % n) + XP * (node / n); }
+  __host__ __device__ static constexpr int sstride(int I) { return I == 0 ? 1 : XP * ipow(n, I - 1); }
+  static constexpr int NSP = NSLOT + (PAIRS ? 0 : 3);
   static constexpr int MP = M;
   template <int NSL>
   __device__ static __forceinline__ int lidx_e(int e, int v) {
@@ -68,7 +77,10 @@ struct Fwd {
   static constexpr bool READ_FIRST = PAIRS || n * M <= 32;
   static constexpr int NGROUP = PAIRS ? 2 : 1;
   static constexpr int group(int c) { return PAIRS ? (c == 0 ? 16 : 32) : 64; }
-  static constexpr int LDS_BUDGET = 80 * 1024;
+  static constexpr int FIN_BYTES = (D + 2) * NS * M * 8;                 // Fbar_i, qbar, V
+                                                                          // (or q, F_i at one time node)
+  // Picard slices: up to 80 KiB, or as much as the finalisation needs anyway.
+  static constexpr int LDS_BUDGET = FIN_BYTES > 80 * 1024 ? FIN_BYTES : 80 * 1024;
   static constexpr int SLICE_BYTES = 2 * NSP * MP * (int)sizeof(Real);
   static constexpr int pick_S() {
     for (int s = n; s > 1; --s)
@@ -84,8 +96,6 @@ struct Fwd {
   static constexpr int NB = (n + S - 1) / S;                 // batches per iteration
   static constexpr int PIC_BYTES = (ALIAS ? 1 : 2) * S * NSP * MP * (int)sizeof(Real);
   static constexpr int FIRST_BYTES = D * NSP * MP * (int)sizeof(Real);   // d flux planes of u
-  static constexpr int FIN_BYTES = (D + 2) * NS * M * 8;                 // Fbar_i, qbar, V
-                                                                          // (or q, F_i at one time node)
   static constexpr int max3(int x, int y, int z) { return x > y ? (x > z ? x : z) : (y > z ? y : z); }
   static constexpr int CELL_BYTES = (max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
@@ -103,7 +113,7 @@ struct Fwd {
 
 template <int D_, int N_, template <int> class PDET, class Real_, bool ST_>
 __device__ __forceinline__ int Fwd<D_, N_, PDET, Real_, ST_>::lidx(int tt, int v, int pos) {
-  return lidx_e<S>(tt * NSP + pos, v);
+  return lidx_e<S>(tt * NSP + slot(pos), v);
 }
 
 // Lane order of the pencil tasks of one axis for a batch of ns time slices.
@@ -127,7 +137,7 @@ constexpr TaskOrder<ns * K::NF> make_task_order() {
   bool used[T] = {};
   for (int task = 0; task < T; ++task) {
     const int tt = task / NF, b = task % NF;
-    off[task] = tt * K::NSP + (b % s) + s * n * (b / s);
+    off[task] = tt * K::NSP + K::slot((b % s) + s * n * (b / s));
   }
   unsigned long long mask[2] = {0ull, 0ull};
   for (int lane = 0; lane < T; ++lane) {
@@ -232,7 +242,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     constexpr int ns = decltype(NS_)::value;
     static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
-      constexpr int sI = ipow(n, I);
+      constexpr int sI = K::sstride(I);
       auto pencil = [&](int e0) {
         Real out[n][M];
         pencil_dF<n, M, Real>(p.t, [&](int j, Real (&F)[M]) {
@@ -279,7 +289,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         Real F[M];
         PDE::template flux_pub<I>(w, F, p.g, cp);
 #pragma unroll
-        for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + a, v)] = F[v];
+        for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + K::slot(a), v)] = F[v];
       });
     }
     __syncthreads();
@@ -288,9 +298,9 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     for (int v = 0; v < M; ++v) rv[v] = Real(0);
     static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
-      constexpr int sI = ipow(n, I);
+      constexpr int sI = K::sstride(I);
       const int ai = coord<n, I>(a);
-      const int e0 = I * NSP + a - ai * sI;
+      const int e0 = I * NSP + K::slot(a) - ai * sI;
 #pragma unroll
       for (int j = 0; j < n; ++j) {
         const Real dj = p.t.D[ai][j];
@@ -314,7 +324,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       const bool act = (ns * NF == NS) || a < ns * NF;
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
-        constexpr int sI = ipow(n, I);
+        constexpr int sI = K::sstride(I);
         const int e0 = e0_of(NS_, I_);
         if (act) {
           pencil_dF<n, M, Real>(p.t, [&](int j, Real (&F)[M]) {
@@ -329,7 +339,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         if (act) {
-          constexpr int sI = ipow(n, I);
+          constexpr int sI = K::sstride(I);
           const int e0 = e0_of(NS_, I_);
           // small pencils: every read before any write (see contract)
           if constexpr (I > 0 && K::READ_FIRST) {
