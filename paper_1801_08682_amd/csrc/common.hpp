@@ -90,27 +90,38 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
 }
 
 // One pencil's contraction out[k][v] = sum_j D[k][j] F_j[v], F_j from
-// flux_at(j, F).  For n >= 5 the even/odd split needs (n/2)(n/2 + 1) + n/2
-// FMAs per variable for the first half of the rows plus 2 n/2 sums and
-// differences each way, instead of n^2: with E_j = F_j + F_{n-1-j} and
-// O_j = F_j - F_{n-1-j} (j < n/2),
+// flux_at(j, F).  For n >= 5 the even/odd split of the centro-antisymmetric D
+// halves the multiplications: with E_j = F_j + F_{n-1-j} and
+// O_j = F_j - F_{n-1-j}, for k, j < n/2
 //   out[k] = S_k + A_k, out[n-1-k] = A_k - S_k, out[n/2] = sum_j Dm[j] O_j,
 //   S_k = sum_j Ce[k][j] E_j + Cm[k] F_{n/2} (odd n), A_k = sum_j Co[k][j] O_j.
+// float: the rounded coefficients no longer sum to zero along a row, so a
+// constant flux would get a derivative of float rounding size.  The float
+// forms therefore contract against a reference flux F_r, which the zero row
+// sums of D allow: n < 5 subtracts F_0; the split takes E_j - 2 F_r with F_r
+// the middle node (odd n, which removes the Cm column) or the middle pair's
+// mean (even n, whose even term then drops).  A constant flux then gives
+// exactly zero.  float64 keeps the plain forms (its rounding is float64's).
 template <int n, int M, class Real, class Tab, class FluxAt>
 __device__ __forceinline__ void pencil_dF(const Tab& t, FluxAt&& flux_at, Real (&out)[n][M]) {
+  constexpr bool REF = !std::is_same<Real, double>::value;
   if constexpr (n < 5) {
+    Real F0[M];
 #pragma unroll
     for (int k = 0; k < n; ++k)
 #pragma unroll
       for (int v = 0; v < M; ++v) out[k][v] = Real(0);
+    if constexpr (REF) flux_at(0, F0);
 #pragma unroll
-    for (int j = 0; j < n; ++j) {
+    for (int j = REF ? 1 : 0; j < n; ++j) {
       Real F[M];
       flux_at(j, F);
 #pragma unroll
-      for (int k = 0; k < n; ++k)
+      for (int v = 0; v < M; ++v) {
+        const Real G = REF ? F[v] - F0[v] : F[v];
 #pragma unroll
-        for (int v = 0; v < M; ++v) out[k][v] = fma(t.D[k][j], F[v], out[k][v]);
+        for (int k = 0; k < n; ++k) out[k][v] = fma(t.D[k][j], G, out[k][v]);
+      }
     }
   } else {
     constexpr int h = n / 2;
@@ -122,29 +133,66 @@ __device__ __forceinline__ void pencil_dF(const Tab& t, FluxAt&& flux_at, Real (
 #pragma unroll
       for (int k = 0; k < h; ++k) S[k][v] = A[k][v] = Real(0);
     }
+    if constexpr (!REF) {
 #pragma unroll
-    for (int j = 0; j < h; ++j) {
-      Real Fa[M], Fb[M];
-      flux_at(j, Fa);
-      flux_at(n - 1 - j, Fb);
+      for (int j = 0; j < h; ++j) {
+        Real Fa[M], Fb[M];
+        flux_at(j, Fa);
+        flux_at(n - 1 - j, Fb);
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-        const Real E = Fa[v] + Fb[v], O = Fa[v] - Fb[v];
+        for (int v = 0; v < M; ++v) {
+          const Real E = Fa[v] + Fb[v], O = Fa[v] - Fb[v];
 #pragma unroll
-        for (int k = 0; k < h; ++k) {
-          S[k][v] = fma(t.Ce[k][j], E, S[k][v]);
-          A[k][v] = fma(t.Co[k][j], O, A[k][v]);
+          for (int k = 0; k < h; ++k) {
+            S[k][v] = fma(t.Ce[k][j], E, S[k][v]);
+            A[k][v] = fma(t.Co[k][j], O, A[k][v]);
+          }
+          if constexpr (odd) Mid[v] = fma(t.Dm[j], O, Mid[v]);
         }
-        if constexpr (odd) Mid[v] = fma(t.Dm[j], O, Mid[v]);
       }
-    }
-    if constexpr (odd) {
-      Real Fm[M];
-      flux_at(h, Fm);
+      if constexpr (odd) {
+        Real Fm[M];
+        flux_at(h, Fm);
 #pragma unroll
-      for (int k = 0; k < h; ++k)
+        for (int k = 0; k < h; ++k)
 #pragma unroll
-        for (int v = 0; v < M; ++v) S[k][v] = fma(t.Cm[k], Fm[v], S[k][v]);
+          for (int v = 0; v < M; ++v) S[k][v] = fma(t.Cm[k], Fm[v], S[k][v]);
+      }
+    } else {
+      Real Er[M];                                  // 2 F_r
+      if constexpr (odd) {
+        Real Fm[M];
+        flux_at(h, Fm);
+#pragma unroll
+        for (int v = 0; v < M; ++v) Er[v] = Real(2) * Fm[v];
+      } else {
+        Real Fa[M], Fb[M];                         // the middle pair: its E is 2 F_r
+        flux_at(h - 1, Fa);
+        flux_at(h, Fb);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          Er[v] = Fa[v] + Fb[v];
+          const Real O = Fa[v] - Fb[v];
+#pragma unroll
+          for (int k = 0; k < h; ++k) A[k][v] = fma(t.Co[k][h - 1], O, A[k][v]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < (odd ? h : h - 1); ++j) {
+        Real Fa[M], Fb[M];
+        flux_at(j, Fa);
+        flux_at(n - 1 - j, Fb);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          const Real E = (Fa[v] + Fb[v]) - Er[v], O = Fa[v] - Fb[v];
+#pragma unroll
+          for (int k = 0; k < h; ++k) {
+            S[k][v] = fma(t.Ce[k][j], E, S[k][v]);
+            A[k][v] = fma(t.Co[k][j], O, A[k][v]);
+          }
+          if constexpr (odd) Mid[v] = fma(t.Dm[j], O, Mid[v]);
+        }
+      }
     }
 #pragma unroll
     for (int k = 0; k < h; ++k)

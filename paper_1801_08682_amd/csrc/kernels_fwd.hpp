@@ -276,9 +276,13 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   // First iteration: q = u on every time node, so sum_i D_i F_i(q) is the
   // same on every slice and P reduces to its row sums.  Every node thread
   // evaluates its d fluxes of u, then gathers sum_i D_i F_i at its own node
-  // from the d pencils through it (all lanes busy, one barrier).
+  // from the d pencils through it (all lanes busy, one barrier).  In float
+  // the gather subtracts the node's own flux first (zero row sums of D), so
+  // that a constant state has exactly zero derivative.
   auto first_iteration = [&]() {
     Real* Fs = reinterpret_cast<Real*>(base);      // [axis][var][node] planes
+    constexpr bool REF = !std::is_same<Real, double>::value;
+    Real Fo[REF ? D : 1][M];
     {
       Real uu[M], w[M];
 #pragma unroll
@@ -289,7 +293,10 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         Real F[M];
         PDE::template flux_pub<I>(w, F, p.g, cp);
 #pragma unroll
-        for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + K::slot(a), v)] = F[v];
+        for (int v = 0; v < M; ++v) {
+          Fs[K::template lidx_e<D>(I * NSP + K::slot(a), v)] = F[v];
+          if constexpr (REF) Fo[I][v] = F[v];
+        }
       });
     }
     __syncthreads();
@@ -305,7 +312,13 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       for (int j = 0; j < n; ++j) {
         const Real dj = p.t.D[ai][j];
 #pragma unroll
-        for (int v = 0; v < M; ++v) rv[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], rv[v]);
+        for (int v = 0; v < M; ++v) {
+          const Real F = Fs[K::template lidx_e<D>(e0 + j * sI, v)];
+          if constexpr (REF)
+            rv[v] = fma(dj, F - Fo[I][v], rv[v]);
+          else
+            rv[v] = fma(dj, F, rv[v]);
+        }
       }
     });
 #pragma unroll

@@ -106,6 +106,25 @@ def test_fp32_predictor_error_is_stated():
     assert max(pf) < 1e-5
 
 
+@pytest.mark.parametrize("prec", [inputs.FP64, inputs.FP32])
+@pytest.mark.parametrize("order", [3, 4, 5, 7])
+def test_uniform_flow_is_kept(order, prec):
+    """A uniform moving state is an exact solution: the derivative of a
+    constant flux must vanish in the predictor's own precision (the float
+    predictor included), so the state after two steps differs from the
+    initial one by float64 round-off only, not by float rounding."""
+    wl = _wl(inputs.EULER, 3, order, (4, 3, 3), (1.4,), prec=prec)
+    rho, u, p = 1.2, np.array([0.3, -0.2, 0.1]), 0.9
+    q = np.concatenate([[rho], rho * u, [p / 0.4 + 0.5 * rho * u @ u]])
+    Q0 = np.broadcast_to(q, (wl.ncells, wl.n ** 3, 5)).copy()
+    print("case uniform flow N", order, "prec", prec, flush=True)
+    Qg, flag, _ = gpu_run(wl, Q0, None, 2, cfl=0.5)
+    assert flag == 0
+    dev = float(np.abs(Qg.numpy() - Q0).max())
+    print("max deviation", dev)
+    assert dev < 1e-13
+
+
 def test_c2_full_size_sampled_parity():
     """C2 at full size (81^3, N=4) in the bench's launch configuration: one
     step on the GPU; 24 sampled cells (corners, edges, bump centre, random)
