@@ -23,6 +23,7 @@ number of steps.
 """
 
 import argparse
+import ctypes
 import json
 import os
 import platform
@@ -36,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DoF-updates/s, 3D Euler N=4: FP64 vs mixed-precision at stated L2 error"
 FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+HBM_PEAK_GBPS = 8000.0
 FP32_PEAK_TFLOPS = 157.3     # published vector fp32 (packed); this path issues unpacked FMAs
 C_DT = 0.99                  # security factor of the optimistic time step (the paper's value)
 
@@ -294,6 +296,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"],
                     help="C2 is the headline line; the others print their own line "
@@ -356,10 +359,14 @@ def main():
         "reruns": reruns,
         "dt_first_last": [float(dts[0]), float(dts[args.steps - 1])],
         "cell_updates_per_s": wl.ncells * args.steps / wall,
+        "legendre_point_updates_per_s": wl.ncells * n ** d * args.steps / wall,
         "roofline": {"kernel": "k_fused (adg_fused_sweep: corrector of step k + predictor of "
                                "step k+1)", "bound": "alu", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
+                     "hbm_frac": wl.ncells * (2 * wl.dofs_per_cell * 8 + 2 * hull * 8)
+                                 / (sweep * 1e-3) / (HBM_PEAK_GBPS * 1e9),
+                     "binding": "alu (FP64 VALU and LDS; hbm_frac is far lower)",
                      "traffic": measured_traffic("k_fused_fp64") if full else None,
                      "traffic_unit": "bytes per launch",
                      "algorithmic_bytes": wl.ncells * (2 * wl.dofs_per_cell * 8 + 2 * hull * 8),
@@ -434,10 +441,66 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = nbytes
+    if not args.no_peaks:
+        print("[bench] measured peaks", file=sys.stderr, flush=True)
+        mp = measured_peaks(torch)
+        out["measured_peaks"] = mp
+        out["roofline"]["frac_of_measured_peak"] = achieved / mp["fp64_fma_TFLOPs"]
+        out["two_kernel"]["correct_hbm"]["frac_of_measured_copy"] = (
+            out["two_kernel"]["correct_hbm"]["achieved_GBps"] / mp["hbm_copy_GBps"])
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
+
+
+def measured_peaks(torch):
+    """Achievable rates on this device for the two resources that bound the
+    step: vector FMA throughput (16 independent chains per thread, 16384
+    workgroups of 256) and streaming HBM bandwidth (copy and triad over
+    2 GiB arrays); best of 5 event-timed launches each."""
+    from paper_1801_08682_amd import _lib
+    P = _lib.load_peaks()
+    stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p(stream.cuda_stream)
+
+    def best(launch, reps=5):
+        launch()                                   # warm-up
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            launch()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return min(ts)
+
+    out = {}
+    blocks, iters = 16384, 12500          # rates still rise up to about 8192 workgroups
+    sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    for prec, name in ((0, "fp64"), (1, "fp32_nonpacked")):
+        def fma():
+            assert P.adg_peak_fma(prec, blocks, iters, ctypes.c_void_p(sink.data_ptr()), h) == 0
+        t = best(fma)
+        out[f"{name}_fma_TFLOPs"] = blocks * 256 * 16 * iters * 2 / t / 1e12
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    def copy():
+        assert P.adg_stream_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(c.data_ptr()), n, h) == 0
+    def triad():
+        assert P.adg_stream_triad(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                  ctypes.c_void_p(c.data_ptr()), 0.5, n, h) == 0
+    out["hbm_copy_GBps"] = 16 * n / best(copy) / 1e9
+    out["hbm_triad_GBps"] = 24 * n / best(triad) / 1e9
+    assert float(c[-1]) == 2.0 and float(c[0]) == 2.0
+    del a, b, c, sink
+    out["note"] = ("published: FP64 vector 78.6 TFLOP/s, FP32 vector 157.3 TFLOP/s, HBM "
+                   "8000 GB/s; the float kernel uses non-packed FMA (packed FP32 instructions are "
+                   "not used in this build)")
+    return out
 
 
 def field_errors(Qa, Qb, W, m, torch):

@@ -9,6 +9,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libadg.so")
+PEAKS_PATH = os.path.join(HERE, "libadg_peaks.so")
+PEAKS_EXPORTS = ["adg_peak_fma", "adg_stream_copy", "adg_stream_triad"]
 
 ADG_OK, ADG_ERR_INVALID_ARG, ADG_ERR_UNSUPPORTED, ADG_ERR_DEVICE, ADG_ERR_WORKSPACE = range(5)
 STATUS_NAMES = {0: "ADG_OK", 1: "ADG_ERR_INVALID_ARG", 2: "ADG_ERR_UNSUPPORTED",
@@ -80,6 +82,29 @@ def load(path=LIB_PATH):
     L.adg_version.argtypes = []
     L.adg_version.restype = ctypes.c_int32
     _lib = L
+    return L
+
+
+_peaks = None
+
+
+def load_peaks(path=PEAKS_PATH):
+    """Load libadg_peaks.so (roofline measurement kernels) once."""
+    global _peaks
+    if _peaks is not None:
+        return _peaks
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_1801_08682_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    for name, args in {"adg_peak_fma": [i32, i32, i32, vp, vp],
+                       "adg_stream_copy": [vp, vp, i64, vp],
+                       "adg_stream_triad": [vp, vp, vp, ctypes.c_double, i64, vp]}.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = i32
+    _peaks = L
     return L
 
 

@@ -1,4 +1,6 @@
-"""Build libadg.so for gfx950 in-tree with hipcc (parallel, one object per unit).
+"""Build libadg.so (the ADER-DG kernels and the C ABI) and libadg_peaks.so
+(roofline measurement kernels) for gfx950 in-tree with hipcc (parallel, one
+object per unit).
 
 Usage: python -m paper_1801_08682_amd.build [-j JOBS]
 """
@@ -14,9 +16,11 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libadg.so")
+PEAKS_LIB = os.path.join(HERE, "libadg_peaks.so")
 
 UNITS = ["api.hip", "tables.cpp", "inst_advection.hip", "inst_euler.hip",
-         "inst_acoustic.hip", "inst_elastic.hip", "adjoint.hip"]
+         "inst_acoustic.hip", "inst_elastic.hip"]
+PEAKS_UNITS = ["peaks.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are switched off for every device compile.
@@ -35,21 +39,25 @@ def _compile(unit):
     return obj
 
 
-def build(jobs=None, verbose=False):
-    """Compile every unit and link libadg.so; returns the library path."""
-    os.makedirs(BUILD, exist_ok=True)
-    units = [u for u in UNITS if os.path.exists(os.path.join(CSRC, u))]
-    jobs = jobs or min(8, os.cpu_count() or 1)
-    with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, units))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs=None, verbose=False):
+    """Compile every unit and link both libraries; returns libadg.so's path."""
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(_compile, UNITS + PEAKS_UNITS))
+    _link(objs[:len(UNITS)], LIB)
+    _link(objs[len(UNITS):], PEAKS_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, PEAKS_LIB)
     return LIB
 
 

@@ -174,3 +174,24 @@ def test_query_spacetime_traces(L):
     c = cfg_of(inputs.preset("C5"))
     c.spacetime_traces = 1
     assert L.adg_query(ctypes.byref(c), None, None, None) == _lib.ADG_ERR_UNSUPPORTED
+
+
+def test_peaks_library_exports_and_validates():
+    """libadg_peaks.so exports what include/adg_peaks.h declares and rejects
+    bad arguments before any launch."""
+    P = _lib.load_peaks()
+    src = open(os.path.join(ROOT, "include", "adg_peaks.h")).read()
+    syms = sorted(set(re.findall(r"^\s*int32_t\s+(adg_\w+)\s*\(", src, re.M)))
+    assert syms == sorted(_lib.PEAKS_EXPORTS)
+    for s in syms:
+        assert hasattr(P, s), s
+    v = ctypes.c_void_p
+    assert P.adg_peak_fma(2, 1, 1, v(256), None) == 1          # precision
+    assert P.adg_peak_fma(0, 0, 1, v(256), None) == 1          # blocks
+    assert P.adg_peak_fma(0, 1, 0, v(256), None) == 1          # iters
+    assert P.adg_peak_fma(0, 1, 1, None, None) == 1            # sink
+    assert P.adg_peak_fma(0, 1, 1, v(8), None) == 1            # alignment
+    assert P.adg_stream_copy(None, None, -1, None) == 1
+    assert P.adg_stream_copy(None, None, 0, None) == 0          # nothing to do
+    assert P.adg_stream_copy(v(8), v(16), 4, None) == 1
+    assert P.adg_stream_triad(v(16), None, v(16), 1.0, 4, None) == 1

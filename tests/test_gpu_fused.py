@@ -42,6 +42,9 @@ CASES = [
     (ACOUSTIC, 3, 2, (4, 3, 3), 4, 0.8, 0.99, True, 1.0),
     (ELASTIC, 2, 3, (5, 4), 4, 0.7, 0.99, True, 1.0),
     (ADVECTION, 2, 3, (5, 6), 4, 0.9, 0.99, True, 1.0),
+    # one cell along an axis: the periodic neighbour is the cell itself
+    (EULER, 3, 4, (1, 1, 1), 3, 0.5, 0.99, True, 0.2),
+    (EULER, 3, 2, (1, 3, 2), 3, 0.5, 0.99, True, 0.2),
 ]
 
 

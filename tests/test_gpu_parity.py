@@ -106,6 +106,27 @@ def test_fp32_predictor_error_is_stated():
     assert max(pf) < 1e-5
 
 
+@pytest.mark.parametrize("pde,dim,order,cells,pp", [
+    (inputs.EULER, 3, 4, (1, 1, 1), (1.4,)),
+    (inputs.EULER, 2, 3, (1, 4), (1.4,)),
+    (inputs.EULER, 3, 7, (1, 2, 1), (1.4,)),
+    (inputs.ELASTIC, 3, 2, (7, 1, 2), ()),
+    (inputs.ACOUSTIC, 3, 3, (1, 2, 1), ()),
+])
+def test_single_cell_axes(pde, dim, order, cells, pp):
+    """One cell along an axis: the periodic neighbour is the cell itself
+    (a single cell is its own neighbour on every face)."""
+    wl = _wl(pde, dim, order, cells, pp)
+    Q0 = inputs.random_state(wl, seed=70 + order, amplitude=0.05)
+    par = inputs.cell_params(wl, seed=71)
+    print("case single-cell axes", pde, dim, order, cells, flush=True)
+    Qg, flag, dg = gpu_run(wl, Q0, par, 3, cfl=0.5, record_dt=True)
+    Qo, do = oracle_run(wl, Q0, par, 3, cfl=0.5)
+    assert flag == 0
+    assert np.allclose(dg, do, rtol=1e-13, atol=0)
+    assert max_rel(Qg, Qo, wl) < TOL64, per_field(Qg, Qo, wl)
+
+
 @pytest.mark.parametrize("prec", [inputs.FP64, inputs.FP32])
 @pytest.mark.parametrize("order", [3, 4, 5, 7])
 def test_uniform_flow_is_kept(order, prec):

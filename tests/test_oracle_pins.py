@@ -361,6 +361,20 @@ def test_translation_by_whole_cells():
     assert (a - b).abs().max() == 0.0
 
 
+@pytest.mark.parametrize("pde", [EULER, ELASTIC])
+def test_single_cell_axes_equal_tiled_grid(pde):
+    """A grid with one cell along an axis (periodic neighbour = the cell
+    itself) steps like the same data tiled twice along that axis."""
+    s1, Q, par = _rand_case(pde, 3, 2, (1, 3, 1), 11)
+    s2 = ostep.Setup(s1.pde_kind, 3, 2, (2, 3, 2), s1.h, s1.pde_param)
+    def tile(X):
+        Y = X.reshape(1, 3, 1, *X.shape[1:]).repeat(2, 1, 2, *([1] * (X.dim() - 1)))
+        return Y.reshape(12, *X.shape[1:])
+    a = ostep.step(Q, par, 0.01, s1)
+    b = ostep.step(tile(Q), None if par is None else tile(par), 0.01, s2)
+    assert (tile(a) - b).abs().max() <= 1e-15 * float(b.abs().max())
+
+
 # ------------------------------------------ P14 step matrix and stability
 def _step_matrix(s, dt, par=None):
     C, nn, m = s.ncells, s.n ** s.dim, s.m
