@@ -297,6 +297,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="print only the C4 adjoint rollout's line")
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"],
                     help="C2 is the headline line; the others print their own line "
@@ -316,11 +318,20 @@ def main():
     from paper_1801_08682_amd import inputs
     from paper_1801_08682_amd.stepper import Stepper
 
+    if args.adjoint_only:
+        res = adjoint_bench(args)
+        if args.copy_calib_mb:
+            res["copy_calib_bytes"] = copy_calibration(args, torch)
+        print(json.dumps(res), flush=True)
+        return
     if args.workload != "C2":
         print(json.dumps(other_workload(args, torch)), flush=True)
         return
     if args.traces == "spacetime":
-        print(json.dumps(spacetime_workload(args, torch)), flush=True)
+        res = spacetime_workload(args, torch)
+        if args.copy_calib_mb:
+            res["copy_calib_bytes"] = copy_calibration(args, torch)
+        print(json.dumps(res), flush=True)
         return
     wl = inputs.preset("C2").with_(n_cells=(args.cells,) * 3,
                                    length=args.cells / 81.0)
@@ -434,13 +445,7 @@ def main():
         print("[bench] adjoint (C4 misfit gradient)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_bench(args)
     if args.copy_calib_mb:
-        nbytes = args.copy_calib_mb << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calib_bytes"] = nbytes
+        out["copy_calib_bytes"] = copy_calibration(args, torch)
     if not args.no_peaks:
         print("[bench] measured peaks", file=sys.stderr, flush=True)
         mp = measured_peaks(torch)
@@ -452,6 +457,18 @@ def main():
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(args, torch):
+    """Three plain device copies of a known size, for scaling the HBM
+    counters of a profiled run."""
+    nbytes = args.copy_calib_mb << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return nbytes
 
 
 def measured_peaks(torch):

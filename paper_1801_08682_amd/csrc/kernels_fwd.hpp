@@ -665,14 +665,20 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
   double* sm = Fs + 2 * D * NF * M;                      // [2D][NT]
   const double cdt = (*p.dt) * p.inv_h;
   if constexpr (K::ST) {
-    // Space-time traces, in two passes over the time nodes of every face task
-    // (the second one finds the traces in L2): the speeds give one s per face
-    // and time node; then F* is integrated in time, sum_t w_t F*(t).
+    // Space-time traces: every trace is read once.  The time loop of each
+    // face task takes the speeds (for one s per face and time node), the
+    // time integral of the mean flux sum_t w_t (fL + fR) / 2 and keeps the
+    // jumps qR - qL in registers; once the maxima are known, the dissipation
+    // sum_t w_t s_t (qR - qL) / 2 is subtracted: F* integrated in time.
+    constexpr int NT = K::NT;
+    double acc[TPT][M], dq[TPT][NT][M];
 #pragma unroll
     for (int v = 0; v < M; ++v) Qn[v] = 1.0;
 #pragma unroll
     for (int r = 0; r < TPT; ++r) {
       const int task = t + r * NTH;
+#pragma unroll
+      for (int v = 0; v < M; ++v) acc[r][v] = 0.0;
       if (live && task < FT) {
         const int f = task / NF, b = task - f * NF;
         const int i = f >> 1, s = f & 1;
@@ -680,29 +686,52 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
         const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
         const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
         const auto pR = PDE::template cell<double>(p.par + cR * K::NPAR);
-#pragma unroll 1
-        for (int tt = 0; tt < K::NT; ++tt) {
-          const int64_t off = (int64_t)tt * K::NQ * NF * M + b * M;
-          const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + off;
-          const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + off;
-          double qL[M], qR[M];
+        const Real* trL0 = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + b * M;
+        const Real* trR0 = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + b * M;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+          const Real* trL = trL0 + (int64_t)tt * K::NQ * NF * M;
+          const Real* trR = trR0 + (int64_t)tt * K::NQ * NF * M;
+          double qL[M], qR[M], fL[M], fR[M];
 #pragma unroll
           for (int v = 0; v < M; ++v) {
             qL[v] = (double)trL[v];
             qR[v] = (double)trR[v];
+            if constexpr (K::NQ == 2) {
+              fL[v] = (double)trL[NF * M + v];
+              fR[v] = (double)trR[NF * M + v];
+            }
           }
           double l = 0.0;
           static_for<0, D>([&](auto I_) {
             constexpr int I = decltype(I_)::value;
-            if (i == I) l = fmax(PDE::template speed<I>(qL, p.g, pL), PDE::template speed<I>(qR, p.g, pR));
+            if (i == I) {
+              if constexpr (K::NQ == 1) {
+                PDE::template flux<I>(qL, fL, p.g, pL);
+                PDE::template flux<I>(qR, fR, p.g, pR);
+              }
+              l = fmax(PDE::template speed<I>(qL, p.g, pL), PDE::template speed<I>(qR, p.g, pR));
+            }
           });
           if (!(l >= 0.0)) bad |= 2;
-          lam[(f * K::NT + tt) * NF + b] = l;
+          lam[(f * NT + tt) * NF + b] = l;
+          const double hw = 0.5 * p.w[tt];
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            acc[r][v] += hw * (fL[v] + fR[v]);
+            dq[r][tt][v] = qR[v] - qL[v];
+            // computed here, not sunk past the barrier below (which would
+            // keep every time node's loaded traces live instead)
+            asm volatile("" : "+v"(acc[r][v]), "+v"(dq[r][tt][v]));
+          }
+          // one time node's loads at a time: the kept jumps already hold
+          // NT M registers per task
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
     __syncthreads();
-    for (int ft = t; ft < 2 * D * K::NT; ft += NTH) {
+    for (int ft = t; ft < 2 * D * NT; ft += NTH) {
       if (live) {
         double sv = 0.0;
         for (int b = 0; b < NF; ++b) sv = fmax(sv, lam[ft * NF + b]);
@@ -714,45 +743,15 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
     for (int r = 0; r < TPT; ++r) {
       const int task = t + r * NTH;
       if (live && task < FT) {
-        const int f = task / NF, b = task - f * NF;
-        const int i = f >> 1, s = f & 1;
-        const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
-        const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
-        const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
-        const auto pR = PDE::template cell<double>(p.par + cR * K::NPAR);
-        double acc[M];
+        const int f = task / NF;
 #pragma unroll
-        for (int v = 0; v < M; ++v) acc[v] = 0.0;
-#pragma unroll 1
-        for (int tt = 0; tt < K::NT; ++tt) {
-          const int64_t off = (int64_t)tt * K::NQ * NF * M + b * M;
-          const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + off;
-          const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + off;
-          double qL[M], qR[M], fL[M], fR[M];
+        for (int tt = 0; tt < NT; ++tt) {
+          const double hs = 0.5 * p.w[tt] * sm[f * NT + tt];
 #pragma unroll
-          for (int v = 0; v < M; ++v) {
-            qL[v] = (double)trL[v];
-            qR[v] = (double)trR[v];
-            if constexpr (K::NQ == 2) {
-              fL[v] = (double)trL[NF * M + v];
-              fR[v] = (double)trR[NF * M + v];
-            }
-          }
-          if constexpr (K::NQ == 1) {
-            static_for<0, D>([&](auto I_) {
-              constexpr int I = decltype(I_)::value;
-              if (i == I) {
-                PDE::template flux<I>(qL, fL, p.g, pL);
-                PDE::template flux<I>(qR, fR, p.g, pR);
-              }
-            });
-          }
-          const double hw = 0.5 * p.w[tt], hs = hw * sm[f * K::NT + tt];
-#pragma unroll
-          for (int v = 0; v < M; ++v) acc[v] += hw * (fL[v] + fR[v]) - hs * (qR[v] - qL[v]);
+          for (int v = 0; v < M; ++v) acc[r][v] -= hs * dq[r][tt][v];
         }
 #pragma unroll
-        for (int v = 0; v < M; ++v) Fs[task * M + v] = acc[v];
+        for (int v = 0; v < M; ++v) Fs[task * M + v] = acc[r][v];
       }
     }
     __syncthreads();
