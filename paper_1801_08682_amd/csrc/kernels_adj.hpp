@@ -74,12 +74,12 @@ __global__ void __launch_bounds__(K::CTHREADS) k_adj_corr(const AdjCorrP<K> p) {
     s = f & 1;
     const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
     const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
-    const double* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b * M;
-    const double* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b * M;
+    const double* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b;
+    const double* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      qL[v] = trL[v];
-      qR[v] = trR[v];
+      qL[v] = trL[v * NF];
+      qR[v] = trR[v * NF];
       dq[v] = qR[v] - qL[v];
       Fb[v] = 0.0;
     }
@@ -143,12 +143,12 @@ __global__ void __launch_bounds__(K::CTHREADS) k_adj_corr(const AdjCorrP<K> p) {
         if constexpr (K::NQ == 1) PDE::template flux_adj<I>(own, tf, tq, pb, p.g, pc);
       }
     });
-    double* out = p.tb + cell * K::TRACE_ELEMS + (int64_t)f * K::NQ * NF * M + b * M;
+    double* out = p.tb + cell * K::TRACE_ELEMS + (int64_t)f * K::NQ * NF * M + b;
 #pragma unroll
-    for (int v = 0; v < M; ++v) out[v] = tq[v];
+    for (int v = 0; v < M; ++v) out[v * NF] = tq[v];
     if constexpr (K::NQ == 2) {
 #pragma unroll
-      for (int v = 0; v < M; ++v) out[NF * M + v] = tf[v];
+      for (int v = 0; v < M; ++v) out[NF * M + v * NF] = tf[v];
     }
   }
   if constexpr (NPAR > 0) {
@@ -366,12 +366,12 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
-        const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb * M;
-        const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb * M;
+        const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb;
+        const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          qbb[v] += p.t.FL[ai] * tl[v] + p.t.FR[ai] * trr[v];
-          Fbb[I][v] = (K::NQ == 2) ? p.t.FL[ai] * tl[NF * M + v] + p.t.FR[ai] * trr[NF * M + v] : 0.0;
+          qbb[v] += p.t.FL[ai] * tl[v * NF] + p.t.FR[ai] * trr[v * NF];
+          Fbb[I][v] = (K::NQ == 2) ? p.t.FL[ai] * tl[NF * M + v * NF] + p.t.FR[ai] * trr[NF * M + v * NF] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < n; ++k) {

@@ -100,7 +100,8 @@ struct Fwd {
   static constexpr int CELL_BYTES = (max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
-  // per cell; layout [face][time][qty][face node][var]
+  // per cell; layout [face][time][qty][var][face node] (face nodes fastest:
+  // a wave writes and reads consecutive face nodes of one variable)
   static constexpr int64_t TRACE_ELEMS = 2LL * D * NT * NQ * NF * M;
   static constexpr int64_t TFACE = (int64_t)NT * NQ * NF * M;   // one face
   // corrector block: one thread per face task and per node
@@ -494,7 +495,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
 #pragma unroll
       for (int k = 0; k < n; ++k) Vs[v * NS + pencil_node<n, I>(b, k)] = vol[k];
       if (!K::ST && live) {
-        Real* tr = p.tr + cs * K::TRACE_ELEMS + b * M + v;
+        Real* tr = p.tr + cs * K::TRACE_ELEMS + v * NF + b;
         Real* tL = tr + (int64_t)(2 * I) * K::TFACE;
         Real* tR = tr + (int64_t)(2 * I + 1) * K::TFACE;
         tL[0] = (Real)qL;
@@ -547,7 +548,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
             }
           }
           if (live) {
-            Real* tr = p.tr + cs * K::TRACE_ELEMS + (int64_t)t * K::NQ * NF * M + b * M + v;
+            Real* tr = p.tr + cs * K::TRACE_ELEMS + (int64_t)t * K::NQ * NF * M + v * NF + b;
             Real* tL = tr + (int64_t)(2 * I) * K::TFACE;
             Real* tR = tr + (int64_t)(2 * I + 1) * K::TFACE;
             tL[0] = (Real)qL;
@@ -686,8 +687,8 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
         const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
         const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
         const auto pR = PDE::template cell<double>(p.par + cR * K::NPAR);
-        const Real* trL0 = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + b * M;
-        const Real* trR0 = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + b * M;
+        const Real* trL0 = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + b;
+        const Real* trR0 = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + b;
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) {
           const Real* trL = trL0 + (int64_t)tt * K::NQ * NF * M;
@@ -695,11 +696,11 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
           double qL[M], qR[M], fL[M], fR[M];
 #pragma unroll
           for (int v = 0; v < M; ++v) {
-            qL[v] = (double)trL[v];
-            qR[v] = (double)trR[v];
+            qL[v] = (double)trL[v * NF];
+            qR[v] = (double)trR[v * NF];
             if constexpr (K::NQ == 2) {
-              fL[v] = (double)trL[NF * M + v];
-              fR[v] = (double)trR[NF * M + v];
+              fL[v] = (double)trL[NF * M + v * NF];
+              fR[v] = (double)trR[NF * M + v * NF];
             }
           }
           double l = 0.0;
@@ -778,15 +779,15 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
       const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
       cLr[r] = cL;
       cRr[r] = cR;
-      const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b * M;
-      const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b * M;
+      const Real* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b;
+      const Real* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b;
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        qL[r][v] = (double)trL[v];
-        qR[r][v] = (double)trR[v];
+        qL[r][v] = (double)trL[v * NF];
+        qR[r][v] = (double)trR[v * NF];
         if constexpr (K::NQ == 2) {
-          fL[r][v] = (double)trL[NF * M + v];
-          fR[r][v] = (double)trR[NF * M + v];
+          fL[r][v] = (double)trL[NF * M + v * NF];
+          fR[r][v] = (double)trR[NF * M + v * NF];
         }
       }
     }
