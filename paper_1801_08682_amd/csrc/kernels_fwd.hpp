@@ -40,13 +40,19 @@ struct Fwd {
   static constexpr int CPB = (NS >= 128) ? 1 : 128 / NS;
   static constexpr int THREADS = CPB * NS;
   // LDS slice layout, as planes indexed by the slot e = tt * NSP + node of a
-  // buffer of NSL time slices.  float64: the variable pairs (v, v+1) in
-  // 16-byte planes [pair][slice][node] and an odd last variable in an 8-byte
-  // plane, so a node's values move as 16-byte words plus at most one 8-byte
-  // word.  float: one plane per variable [var][slice][node], stride padded
-  // by 3.  The pencil tasks are dealt to the lanes in the order of
-  // TaskOrder below, which keeps every access free of bank conflicts.
-  static constexpr bool PAIRS = std::is_same<Real, double>::value;
+  // buffer of NSL time slices.  Packed: the variables in groups of VEC
+  // (2 float64, 4 float) in 16-byte planes [group][slice][node] and the
+  // remaining ones in planes of one variable [var][slice][node], so a node's
+  // values move as 16-byte words.  Otherwise one plane per variable, stride
+  // padded by 3.  float64 is always packed; float is packed for the linear
+  // PDEs (measured faster there, slower for Euler, whose float kernel pairs
+  // its 4-byte accesses as it is).  The pencil tasks are dealt to the lanes
+  // in the order of TaskOrder below, which keeps every access free of bank
+  // conflicts.
+  static constexpr bool DBL = std::is_same<Real, double>::value;
+  static constexpr int VEC = DBL ? 2 : 4;               // values per 16-byte word
+  static constexpr int NV = M / VEC;                    // 16-byte words per node
+  static constexpr bool PACKED = DBL || (NV > 0 && PDE::LINEAR);
   // Slots of a slice: node (x, rest) sits at slot x + XP * rest.  When n is a
   // multiple of 4 every x-row is padded to n + 1 slots: the pencils along x
   // then start n + 1 slots apart, an odd stride, where n apart would put
@@ -56,14 +62,13 @@ struct Fwd {
   static constexpr int NSLOT = XP * NF;
   __host__ __device__ static constexpr int slot(int node) { return (node % n) + XP * (node / n); }
   __host__ __device__ static constexpr int sstride(int I) { return I == 0 ? 1 : XP * ipow(n, I - 1); }
-  static constexpr int NSP = NSLOT + (PAIRS ? 0 : 3);
+  static constexpr int NSP = NSLOT + (PACKED ? 0 : 3);
   static constexpr int MP = M;
   template <int NSL>
   __device__ static __forceinline__ int lidx_e(int e, int v) {
-    if constexpr (PAIRS) {
-      constexpr int NP2 = M / 2;
-      if (v < 2 * NP2) return ((v >> 1) * NSL * NSP + e) * 2 + (v & 1);
-      return 2 * NP2 * NSL * NSP + e;
+    if constexpr (PACKED) {
+      if (v < NV * VEC) return ((v / VEC) * NSL * NSP + e) * VEC + (v % VEC);
+      return (NV * VEC + (v - NV * VEC)) * NSL * NSP + e;
     } else {
       return v * NSL * NSP + e;
     }
@@ -74,9 +79,9 @@ struct Fwd {
   // Axis sums of a pencil (n m values): all reads before the writes, except
   // for large float pencils, where the extra live values cost more waves
   // than the serialised node-by-node read-modify-write.
-  static constexpr bool READ_FIRST = PAIRS || n * M <= 32;
-  static constexpr int NGROUP = PAIRS ? 2 : 1;
-  static constexpr int group(int c) { return PAIRS ? (c == 0 ? 16 : 32) : 64; }
+  static constexpr bool READ_FIRST = DBL || n * M <= 32;
+  static constexpr int NGROUP = PACKED ? 2 : 1;
+  static constexpr int group(int c) { return PACKED ? (c == 0 ? 16 : (DBL ? 32 : 64)) : 64; }
   static constexpr int FIN_BYTES = (D + 2) * NS * M * 8;                 // Fbar_i, qbar, V
                                                                           // (or q, F_i at one time node)
   // Picard slices: up to 80 KiB, or as much as the finalisation needs anyway.
