@@ -74,14 +74,18 @@ struct Fwd {
     }
   }
   __device__ static __forceinline__ int lidx(int tt, int v, int pos);
-  // Lanes the LDS serves per cycle for this layout's accesses: 16-byte words
-  // 16 lanes, 8-byte words 32 lanes, 4-byte words 64 lanes (64 banks of 4 B).
+  // Lanes the LDS serves per pass for this layout's accesses (64 banks of
+  // 4 B; measured): reads of 16-byte words 16 lanes, of 8-byte words 32, of
+  // 4-byte words 64; writes of 16-byte words 8 lanes, of 8-byte words 16.  A
+  // group of G lanes is conflict-free when its words are distinct modulo G.
   // Axis sums of a pencil (n m values): all reads before the writes, except
   // for large float pencils, where the extra live values cost more waves
   // than the serialised node-by-node read-modify-write.
   static constexpr bool READ_FIRST = DBL || n * M <= 32;
-  static constexpr int NGROUP = PACKED ? 2 : 1;
-  static constexpr int group(int c) { return PACKED ? (c == 0 ? 16 : (DBL ? 32 : 64)) : 64; }
+  static constexpr int NGROUP = PACKED ? 3 : 1;
+  static constexpr int group(int c) {
+    return PACKED ? (c == 0 ? 8 : (c == 1 ? 16 : (DBL ? 32 : 64))) : 64;
+  }
   static constexpr int FIN_BYTES = (D + 2) * NS * M * 8;                 // Fbar_i, qbar, V
                                                                           // (or q, F_i at one time node)
   // Picard slices: up to 80 KiB, or as much as the finalisation needs anyway.
@@ -127,8 +131,8 @@ __device__ __forceinline__ int Fwd<D_, N_, PDET, Real_, ST_>::lidx(int tt, int v
 // lane reads and writes the slots e0 + j n^I, j = 0..n-1, with e0 its first
 // node.  Greedy order: each lane takes the first unused task whose e0 is
 // distinct, modulo G, from the e0 of the lanes before it in its aligned
-// group of G lanes, for every G the layout's accesses are served in (fewer
-// constraints when none fits).  The offsets j n^I are the same on every
+// group of G lanes, for every G the layout's reads and writes are served in
+// (the last constraints dropped first when none fits).  The offsets j n^I are the same on every
 // lane, so one order serves the whole pencil.
 template <int T>
 struct TaskOrder {
@@ -145,7 +149,7 @@ constexpr TaskOrder<ns * K::NF> make_task_order() {
     const int tt = task / NF, b = task % NF;
     off[task] = tt * K::NSP + K::slot((b % s) + s * n * (b / s));
   }
-  unsigned long long mask[2] = {0ull, 0ull};
+  unsigned long long mask[3] = {0ull, 0ull, 0ull};
   for (int lane = 0; lane < T; ++lane) {
     for (int c = 0; c < K::NGROUP; ++c)
       if (lane % K::group(c) == 0) mask[c] = 0ull;
