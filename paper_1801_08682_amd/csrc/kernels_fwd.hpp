@@ -43,12 +43,14 @@ struct Fwd {
   // buffer of NSL time slices.  Packed: the variables in groups of VEC
   // (2 float64, 4 float) in 16-byte planes [group][slice][node] and the
   // remaining ones in planes of one variable [var][slice][node], so a node's
-  // values move as 16-byte words.  Otherwise one plane per variable, stride
-  // padded by 3.  float64 is always packed; float is packed for the linear
-  // PDEs (measured faster there, slower for Euler, whose float kernel pairs
-  // its 4-byte accesses as it is).  The pencil tasks are dealt to the lanes
-  // in the order of TaskOrder below, which keeps every access free of bank
-  // conflicts.
+  // values move as 16-byte words.  Otherwise one plane per variable.
+  // float64 is always packed; float is packed for the linear PDEs (measured
+  // faster there, slower for Euler, whose float kernel pairs its 4-byte
+  // accesses as it is).  Slices are not padded: a slice stride that is a
+  // multiple of 64 words (the float C2 stride padded by 3 was 128) puts the
+  // two time slices of a paired access on one bank.  The pencil tasks are
+  // dealt to the lanes in the order of TaskOrder below, which keeps every
+  // pencil access free of bank conflicts.
   static constexpr bool DBL = std::is_same<Real, double>::value;
   static constexpr int VEC = DBL ? 2 : 4;               // values per 16-byte word
   static constexpr int NV = M / VEC;                    // 16-byte words per node
@@ -62,7 +64,7 @@ struct Fwd {
   static constexpr int NSLOT = XP * NF;
   __host__ __device__ static constexpr int slot(int node) { return (node % n) + XP * (node / n); }
   __host__ __device__ static constexpr int sstride(int I) { return I == 0 ? 1 : XP * ipow(n, I - 1); }
-  static constexpr int NSP = NSLOT + (PACKED ? 0 : 3);
+  static constexpr int NSP = NSLOT;
   static constexpr int MP = M;
   template <int NSL>
   __device__ static __forceinline__ int lidx_e(int e, int v) {
@@ -75,9 +77,10 @@ struct Fwd {
   }
   __device__ static __forceinline__ int lidx(int tt, int v, int pos);
   // Lanes the LDS serves per pass for this layout's accesses (64 banks of
-  // 4 B; measured): reads of 16-byte words 16 lanes, of 8-byte words 32, of
-  // 4-byte words 64; writes of 16-byte words 8 lanes, of 8-byte words 16.  A
-  // group of G lanes is conflict-free when its words are distinct modulo G.
+  // 4 B; measured): reads take 256 bytes per pass (16-byte words 16 lanes,
+  // 8-byte words 32, 4-byte words 64), writes 128 bytes (8, 16 and 32
+  // lanes).  A group of G lanes is conflict-free when its words are distinct
+  // modulo G.
   // Axis sums of a pencil (n m values): all reads before the writes, except
   // for large float pencils, where the extra live values cost more waves
   // than the serialised node-by-node read-modify-write.
