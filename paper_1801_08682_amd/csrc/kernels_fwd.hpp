@@ -85,9 +85,9 @@ struct Fwd {
   // for large float pencils, where the extra live values cost more waves
   // than the serialised node-by-node read-modify-write.
   static constexpr bool READ_FIRST = DBL || n * M <= 32;
-  static constexpr int NGROUP = PACKED ? 3 : 1;
+  static constexpr int NGROUP = PACKED ? 3 : 2;
   static constexpr int group(int c) {
-    return PACKED ? (c == 0 ? 8 : (c == 1 ? 16 : (DBL ? 32 : 64))) : 64;
+    return PACKED ? (c == 0 ? 8 : (c == 1 ? 16 : (DBL ? 32 : 64))) : (c == 0 ? 32 : 64);
   }
   static constexpr int FIN_BYTES = (D + 2) * NS * M * 8;                 // Fbar_i, qbar, V
                                                                           // (or q, F_i at one time node)
