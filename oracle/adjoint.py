@@ -48,7 +48,7 @@ def grad_misfit(Q0, par, s, dts, points, data):
     p = None if par is None else par.clone().requires_grad_(True)
     J = misfit(Q0, p, s, dts, points, data)
     gs = torch.autograd.grad(J, [Q0] + ([p] if p is not None else []))
-    return float(J), gs[0], (gs[1] if p is not None else None)
+    return float(J.detach()), gs[0], (gs[1] if p is not None else None)
 
 
 def grad_final_ke(Q0, s, dts):
@@ -57,7 +57,7 @@ def grad_final_ke(Q0, s, dts):
     QN, _ = rollout(Q0, None, s, dts)
     J = kinetic_energy(QN, s)
     (g,) = torch.autograd.grad(J, [Q0])
-    return float(J), g
+    return float(J.detach()), g
 
 
 def step_vjp(Q, par, dt, s, G):

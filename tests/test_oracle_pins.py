@@ -190,31 +190,82 @@ def test_picard_exact_termination(d, N):
 
 
 # ------------------------------------------------------- P5 weak-form residual
-def test_converged_predictor_solves_space_time_weak_form():
-    """P5: the converged Picard solution (Euler, 2D, N=2) satisfies the
-    cell-local space-time weak form of Eq. (3) with upwind initial data,
-    evaluated by exact integration of root-built Lagrange polynomials."""
-    N, d = 2, 2
+def _lagrange_product_form(xi, x):
+    """phi_b(x) and phi_b'(x) from the product formula (not the barycentric
+    form the oracle uses); x is an array of points."""
+    n = len(xi)
+    V = np.ones((len(x), n))
+    dV = np.zeros((len(x), n))
+    for b in range(n):
+        for k in range(n):
+            if k != b:
+                V[:, b] *= (x - xi[k]) / (xi[b] - xi[k])
+        for j in range(n):
+            if j == b:
+                continue
+            t = np.full(len(x), 1.0 / (xi[b] - xi[j]))
+            for k in range(n):
+                if k != b and k != j:
+                    t *= (x - xi[k]) / (xi[b] - xi[k])
+            dV[:, b] += t
+    return V, dV
+
+
+def _galerkin_1d(xi, nq=24):
+    """Mass Mm[a][b] = int phi_a phi_b, Gd[a][b] = int phi_a phi_b' on [0, 1]
+    and phi(0), by a 24-point Gauss rule (exact for these degrees) applied to
+    the product-form basis."""
+    z, om = np.polynomial.legendre.leggauss(nq)
+    x, w = 0.5 * (1.0 + z), 0.5 * om
+    V, dV = _lagrange_product_form(xi, x)
+    return (V * w[:, None]).T @ V, (V * w[:, None]).T @ dV, _lagrange_product_form(xi, np.zeros(1))[0][0]
+
+
+def _along(M, x, ax):
+    return np.moveaxis(np.tensordot(M, x, axes=([1], [ax])), 0, ax)
+
+
+def _weak_form_residual(q, u, F, dt, h, Mm, Gd, th0, flux_sign=1.0):
+    """Residual of Eq. (3) for one cell, tested with theta_k(tau) phi_a(x),
+    with the cell state u as the upwind value at tau = 0 and the collocated
+    flux values F_i (reading R4), in the form
+      int theta_k phi_a (dq/dtau + (dt/h) sum_i dF_i/dxi_i) + theta_k(0) int phi_a (q(0) - u).
+    q, F_i: (t, k_{d-1}, .., k_0, m); u: (k_{d-1}, .., k_0, m)."""
+    d = u.ndim - 1
+    def kron(mats, X):          # mats[0] along time, mats[1 + a] along tensor axis 1 + a
+        for ax, M in enumerate(mats):
+            X = _along(M, X, ax)
+        return X
+    r = kron([Gd] + [Mm] * d, q)
+    for i in range(d):                       # spatial axis i sits at tensor axis d - i
+        mats = [Mm] + [Mm] * d
+        mats[d - i] = Gd
+        r = r + flux_sign * (dt / h) * kron(mats, F[i])
+    q0 = np.tensordot(th0, q, axes=([0], [0]))
+    r = r + th0.reshape((-1,) + (1,) * (d + 1)) * kron([Mm] * d, q0 - u)[None]
+    return r
+
+
+@pytest.mark.parametrize("d,N", [(2, 2), (3, 4), (3, 7)])
+def test_converged_predictor_solves_space_time_weak_form(d, N):
+    """P5: the converged Picard solution (Euler; 2D N=2 and one 3D cell at the
+    headline order N=4 and at N=7) satisfies the cell-local space-time weak
+    form of Eq. (3) with upwind initial data and collocated fluxes, evaluated
+    with the product-form Lagrange basis and a 24-point Gauss rule.  A flipped
+    flux sign leaves a residual of the size of the flux terms."""
     n = N + 1
-    s = ostep.Setup(EULER, d, N, (1, 1), 0.2, (1.4,))
-    wl = inputs.Workload("p5", inputs.EULER, d, N, (1, 1), 0.2, (1.4,))
-    u = torch.tensor(inputs.random_state(wl, seed=3, amplitude=0.2)).reshape(1, n, n, 4)
-    dt = 0.05
-    q = ostep.predictor(u, None, dt, s, tol=1e-15)[0]        # (t, k_y, k_x, m)
-    phi = lagrange_polys(s.tab.xi)
-    Mm = np.array([[integ01(phi[a] * phi[b]) for b in range(n)] for a in range(n)])
-    Gd = np.array([[integ01(phi[a] * phi[b].deriv()) for b in range(n)] for a in range(n)])
-    th0 = np.array([p(0.0) for p in phi])
-    F = [s.pde.flux(q, i, None).numpy() for i in range(d)]   # collocated flux values
-    qn = q.numpy()
-    un = u[0].numpy()
-    # r[k, by, bx, v]
-    r = np.einsum("kl,yY,xX,lYXv->kyxv", Gd, Mm, Mm, qn)
-    r += (dt / s.h) * np.einsum("kl,yY,xX,lYXv->kyxv", Mm, Mm, Gd, F[0])
-    r += (dt / s.h) * np.einsum("kl,yY,xX,lYXv->kyxv", Mm, Gd, Mm, F[1])
-    q0 = np.einsum("l,lyxv->yxv", th0, qn)
-    r += np.einsum("k,yY,xX,YXv->kyxv", th0, Mm, Mm, q0 - un)
+    nc = (1,) * d
+    s = ostep.Setup(EULER, d, N, nc, 0.2, (1.4,))
+    wl = inputs.Workload("p5", inputs.EULER, d, N, nc, 0.2, (1.4,))
+    u = torch.tensor(inputs.random_state(wl, seed=3, amplitude=0.2)).reshape(1, *([n] * d), d + 2)
+    dt = 0.05 if d == 2 else (0.01 if N < 7 else 0.002)
+    q = ostep.predictor(u, None, dt, s, tol=1e-16, max_iters=400)[0]
+    Mm, Gd, th0 = _galerkin_1d(s.tab.xi)
+    F = [s.pde.flux(q, i, None).numpy() for i in range(d)]
+    r = _weak_form_residual(q.numpy(), u[0].numpy(), F, dt, s.h, Mm, Gd, th0)
     assert np.abs(r).max() < 1e-13
+    bad = _weak_form_residual(q.numpy(), u[0].numpy(), F, dt, s.h, Mm, Gd, th0, flux_sign=-1.0)
+    assert np.abs(bad).max() > 1e-5
 
 
 # ----------------------------------------------------- P6, P7 invariants
@@ -397,25 +448,87 @@ def test_linear_step_matrix_conservation_and_consistency():
     assert np.abs(S @ np.ones(S.shape[0]) - 1).max() < 1e-14
 
 
-def _grows(s, dt, steps=1500, seed=0):
-    Q = torch.tensor(np.random.default_rng(seed).standard_normal((s.ncells, s.n ** s.dim, 1)))
-    n0 = float(Q.norm())
-    for _ in range(steps):
-        Q = ostep.step(Q, None, dt, s)
-        if not torch.isfinite(Q).all() or float(Q.norm()) > 1e3 * n0:
-            return True
-    return float(Q.norm()) > 2 * n0
+def _symbol_blocks(s, dt):
+    """Blocks S[c] = d(step cell c)/d(cell 0) of the linear step, from the step
+    applied to every unit vector supported on cell 0 (3 cells per used axis:
+    one step couples face neighbours only, so the offsets -1, 0, +1 do not
+    alias), restricted to the nodes with k_j = 0 on the axes without
+    transport (their data only ride along)."""
+    C, nn, m = s.ncells, s.n ** s.dim, s.m
+    cols = []
+    for k in range(nn * m):
+        e = torch.zeros(C * nn * m, dtype=torch.float64)
+        e[k] = 1.0
+        cols.append(ostep.step(e.view(C, nn, m), None, dt, s).reshape(C, nn * m))
+    return torch.stack(cols, -1).numpy()
+
+
+def _spectral_radius(s, dt, axes, nth):
+    """max over the wavenumbers theta of the spectral radius of the
+    amplification matrix G(theta) = sum_c S[c] exp(-i theta . offset(c))
+    (von Neumann analysis of the periodic step; sampled on nth points per
+    transported axis)."""
+    B = _symbol_blocks(s, dt)
+    n = s.n
+    keep = [a for a in range(n ** s.dim)
+            if all(((a // n ** i) % n) == 0 for i in range(s.dim) if i not in axes)]
+    B = B[:, keep][:, :, keep]
+    offs = []
+    for c in range(s.ncells):
+        o, r = [], c
+        for i in range(s.dim):
+            x = r % s.n_cells[i]
+            r //= s.n_cells[i]
+            o.append(x if x <= s.n_cells[i] // 2 else x - s.n_cells[i])
+        offs.append(o)
+    offs = np.array(offs, dtype=np.float64)
+    th = np.linspace(0.0, 2 * np.pi, nth, endpoint=False)
+    best = 0.0
+    for t in itertools.product(*[th if i in axes else [0.0] for i in range(s.dim)]):
+        G = np.tensordot(np.exp(-1j * (offs @ np.array(t))), B, axes=(0, 0))
+        best = max(best, float(np.abs(np.linalg.eigvals(G)).max()))
+    return best
+
+
+def _rho_1d(N, C):
+    s = ostep.Setup(ADVECTION, 2, N, (3, 1), 1 / 3, (1.0, 0.0))
+    return _spectral_radius(s, C * s.h / (2 * N + 1), axes=(0,), nth=256)
 
 
 @pytest.mark.parametrize("N", [3, 4, 7])
 def test_time_step_stability_limit(N):
-    """P14 (von Neumann by long runs): with equal-speed axes the stated rule
-    dt = 0.9 h / (d (2N+1) lambda) is unstable for N >= 3 (round-off grows
-    without bound), while 0.9 of the measured limit C_N is stable.  This pins
-    the time-step reading used by the workloads."""
-    s = ostep.Setup(ADVECTION, 2, N, (8, 1), 1 / 8, (1.0, 0.0))
-    assert _grows(s, 0.9 * s.h / (2 * N + 1) * (1.0 if N > 3 else 1.1))
-    assert not _grows(s, inputs.stable_cfl(N) * s.h / (2 * N + 1))
+    """P14 (von Neumann): spectral radius rho of the periodic linear-advection
+    step, dt = C h / ((2N+1) |a|).  The stated C = 0.9 is unstable for
+    N >= 3 (rho = 1.55, 2.16, 5.55 for N = 3, 4, 7).  The limits C_N of the
+    workload rule: N = 3 is exactly stable up to C_3 = 0.725 (rho <= 1 to
+    round-off; the bisected limit is 0.7275); for N >= 4 the step has a
+    weak growth at every C (rho - 1 ~ C^2: 4.3e-6 per step at the N = 4
+    preset C = 0.9 C_4, 1.1e-4 at N = 7), and C_N marks where it jumps by
+    orders of magnitude (rho >= 1.05 just above it)."""
+    CN = inputs.STABLE_C[N]
+    assert _rho_1d(N, 0.9) > 1.5
+    if N == 3:
+        assert _rho_1d(N, CN) <= 1 + 1e-12
+        assert _rho_1d(N, 0.9 * CN) <= 1 + 1e-12
+        assert _rho_1d(N, 1.015 * CN) > 1 + 1e-4
+    else:
+        weak = {4: 1e-5, 7: 2e-4}[N]
+        r = _rho_1d(N, 0.9 * CN)
+        assert 1.0 < r < 1 + weak
+        assert _rho_1d(N, CN) < 1 + weak
+        assert _rho_1d(N, 1.05 * CN) > 1.05
+    if N == 4:   # growth of the weakest mode over the 100 steps of the Euler N = 4 workload
+        assert _rho_1d(N, 0.9 * CN) ** 100 < 1 + 1e-3
+
+
+def test_equal_speed_2d_stability():
+    """P14 in 2D with equal speeds a = (1, 1) and the rule
+    dt = C h / (d (2N+1) |a|_max): at N = 3 the stated C = 0.9 is unstable
+    (rho = 1.61) and 0.9 C_3 is stable to round-off."""
+    s = ostep.Setup(ADVECTION, 2, 3, (3, 3), 1 / 3, (1.0, 1.0))
+    dt = lambda C: C * s.h / (2 * 7)
+    assert _spectral_radius(s, dt(0.9), axes=(0, 1), nth=32) > 1.5
+    assert _spectral_radius(s, dt(inputs.stable_cfl(3)), axes=(0, 1), nth=32) <= 1 + 1e-12
 
 
 # --------------------------------------------------- flux / wave-speed pins

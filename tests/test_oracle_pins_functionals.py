@@ -1,0 +1,177 @@
+"""Pins of the oracle's diagnostics and functionals (CPU only): kinetic
+energy, receiver basis rows and sampling, and the misfit.
+
+Expected values come from closed-form polynomial algebra on the physical
+domain (numpy polynomials, exact monomial integrals), not from the oracle's
+Gauss-Legendre tables or its barycentric evaluation.
+"""
+
+import itertools
+
+import numpy as np
+import torch
+
+from oracle import step as ostep
+from oracle.adjoint import misfit, receiver_sampler, rollout
+from oracle.diagnostics import basis_rows, kinetic_energy, point_values
+from oracle.pde import ACOUSTIC, EULER
+from paper_1801_08682_amd import inputs
+
+
+def _poly(c, X):
+    """sum_alpha c[alpha] prod_i X_i^alpha_i at points X (..., d)."""
+    out = np.zeros(X.shape[:-1])
+    for idx in itertools.product(*[range(k) for k in c.shape]):
+        t = c[idx]
+        for i, e in enumerate(idx):
+            t = t * X[..., i] ** e
+        out = out + t
+    return out
+
+
+def _poly_mul(a, b):
+    """Coefficients of the product of two polynomials in d variables."""
+    out = np.zeros(tuple(x + y - 1 for x, y in zip(a.shape, b.shape)))
+    for ia in itertools.product(*[range(k) for k in a.shape]):
+        for ib in itertools.product(*[range(k) for k in b.shape]):
+            out[tuple(x + y for x, y in zip(ia, ib))] += a[ia] * b[ib]
+    return out
+
+
+def _box_integral(c, L):
+    """Exact integral over [0, L_0] x .. of sum c[alpha] x^alpha."""
+    tot = 0.0
+    for idx in itertools.product(*[range(k) for k in c.shape]):
+        t = c[idx]
+        for i, e in enumerate(idx):
+            t *= L[i] ** (e + 1) / (e + 1)
+        tot += t
+    return tot
+
+
+def test_kinetic_energy_exact_integral():
+    """KE = int |j|^2 / (2 rho) dx for rho = 2 and a momentum field that is a
+    polynomial of degree <= N per axis on a 3 x 2 x 4 grid: |j|^2 has degree
+    2N per axis, which the N+1 Gauss points integrate exactly.  Pins the cell
+    volume h^d, the tensor weights, the factor 1/2, the division by rho and
+    the sum over the d momentum components.  Doubling rho halves KE."""
+    N, d = 3, 3
+    nc = (3, 2, 4)
+    h = 0.25
+    wl = inputs.Workload("ke", inputs.EULER, d, N, nc, nc[0] * h, (1.4,))
+    s = ostep.Setup(EULER, d, N, nc, h, (1.4,))
+    X = inputs.node_positions(wl)
+    rng = np.random.default_rng(21)
+    coef = [rng.standard_normal((N + 1,) * d) for _ in range(d)]
+    Q = np.zeros(X.shape[:2] + (d + 2,))
+    Q[..., 0] = 2.0
+    for k in range(d):
+        Q[..., 1 + k] = _poly(coef[k], X)
+    Q[..., d + 1] = 7.0
+    L = [nc[i] * h for i in range(d)]
+    exact = sum(_box_integral(_poly_mul(c, c), L) for c in coef) / (2 * 2.0)
+    ke = float(kinetic_energy(torch.tensor(Q), s))
+    assert abs(ke - exact) < 1e-13 * abs(exact)
+    Q[..., 0] = 4.0
+    assert abs(float(kinetic_energy(torch.tensor(Q), s)) - exact / 2) < 1e-13 * abs(exact)
+
+
+def _poly_state(wl, rng, m):
+    X = inputs.node_positions(wl)
+    coefs = [rng.standard_normal((wl.n,) * wl.dim) for _ in range(m)]
+    Q = np.stack([_poly(c, X) for c in coefs], -1)
+    return Q, coefs
+
+
+def test_basis_rows_and_receivers_reproduce_polynomials():
+    """basis_rows / receiver_sampler: on a 3 x 2 x 4 grid with a state that
+    is one polynomial of degree <= N per axis over the whole box (so every
+    cell holds it exactly), sampling at random points, including one past
+    the domain end and one at a negative coordinate (periodic wrap),
+    returns the polynomial's closed-form value for the selected variable.
+    A wrong cell index, axis order or variable would not."""
+    N, d = 3, 3
+    nc = (3, 2, 4)
+    h = 0.25
+    wl = inputs.Workload("rcv", inputs.ACOUSTIC, d, N, nc, nc[0] * h)
+    s = ostep.Setup(ACOUSTIC, d, N, nc, h)
+    rng = np.random.default_rng(22)
+    Q, coefs = _poly_state(wl, rng, 4)
+    L = np.array([nc[i] * h for i in range(d)])
+    pts = rng.uniform(0.0, 1.0, size=(20, d)) * L
+    pts = np.concatenate([pts, [[0.1, 0.2, 0.3] + L * np.array([1.0, 0.0, 0.0]),
+                                [-0.05, 0.4, 0.9]]])
+    wrapped = pts % L
+    Qt = torch.tensor(Q)
+    for var in (0, 2):
+        v = receiver_sampler(s, pts, var=var)(Qt).numpy()
+        assert np.allclose(v, _poly(coefs[var], wrapped), rtol=0, atol=1e-12)
+    cells, rows = basis_rows(s, pts)
+    ix = np.floor(wrapped / h).astype(int)
+    assert np.array_equal(cells, ix[:, 0] + nc[0] * (ix[:, 1] + nc[1] * ix[:, 2]))
+    assert np.allclose(rows.sum(1).numpy(), 1.0, atol=1e-13)   # partition of unity
+    pv = point_values(Qt, s, pts).numpy()
+    assert np.allclose(pv[:, 3], _poly(coefs[3], wrapped), rtol=0, atol=1e-12)
+
+
+def test_misfit_on_a_steady_state():
+    """misfit: a uniform acoustic state (p = p0, u = 0) is steady, so every
+    sample equals p0 and J = 1/2 sum_n sum_r (p0 - d_{r,n})^2 exactly; the
+    rollout keeps the state to round-off."""
+    N, d = 2, 3
+    nc = (2, 2, 3)
+    h = 1.0 / 3
+    s = ostep.Setup(ACOUSTIC, d, N, nc, h)
+    C, nn = s.ncells, s.n ** d
+    p0 = 0.7
+    Q0 = torch.zeros(C, nn, 4, dtype=torch.float64)
+    Q0[..., 0] = p0
+    par = torch.full((C, 1), 1.05, dtype=torch.float64)
+    rng = np.random.default_rng(23)
+    pts = rng.uniform(0, 1, size=(5, d)) * np.array([nc[i] * h for i in range(d)])
+    dts = [0.01, 0.012, 0.009]
+    data = torch.tensor(rng.standard_normal((len(dts), len(pts))))
+    J = float(misfit(Q0, par, s, dts, pts, data))
+    assert abs(J - 0.5 * float(((p0 - data) ** 2).sum())) < 1e-13
+    QN, smp = rollout(Q0, par, s, dts, receiver_sampler(s, pts))
+    assert (QN - Q0).abs().max() < 1e-14
+    assert smp.shape == (len(dts), len(pts))
+
+
+def test_oracle_gradients_match_central_differences():
+    """The oracle's reverse mode (autograd through its steps, dt held fixed):
+    dJ/dQ0 and dJ/dc of the receiver misfit (acoustics) and dKE/dQ0 (Euler)
+    agree with central differences along seeded directions."""
+    from oracle.adjoint import grad_final_ke, grad_misfit
+    rng = np.random.default_rng(3)
+    # misfit, acoustics N=2 on 2 x 2 x 2 cells, 3 steps
+    wl = inputs.Workload("g", inputs.ACOUSTIC, 3, 2, (2, 2, 2), 1.0)
+    s = ostep.Setup(ACOUSTIC, 3, 2, (2, 2, 2), 0.5)
+    Q0 = torch.tensor(inputs.random_state(wl, seed=4))
+    par = torch.tensor(inputs.cell_params(wl, seed=0))
+    pts = inputs.receivers(4, 3, seed=1)
+    dts = [0.01, 0.011, 0.009]
+    data = torch.tensor(rng.standard_normal((3, 4)))
+    J, gQ, gp = grad_misfit(Q0, par, s, dts, pts, data)
+    for _ in range(3):
+        v = torch.tensor(rng.standard_normal(Q0.shape))
+        w = torch.tensor(rng.standard_normal(par.shape))
+        eps = 1e-6
+        fd = (float(misfit(Q0 + eps * v, par + eps * w, s, dts, pts, data)) -
+              float(misfit(Q0 - eps * v, par - eps * w, s, dts, pts, data))) / (2 * eps)
+        an = float((gQ * v).sum() + (gp * w).sum())
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    # final kinetic energy, Euler N=2 on 2 x 2 x 1 cells, 2 steps
+    wl = inputs.Workload("k", inputs.EULER, 3, 2, (2, 2, 1), 1.0, (1.4,))
+    s = ostep.Setup(EULER, 3, 2, (2, 2, 1), 0.5, (1.4,))
+    Q0 = torch.tensor(inputs.random_state(wl, seed=6, amplitude=0.2))
+    dts = [0.01, 0.012]
+    KE, g = grad_final_ke(Q0, s, dts)
+    def ke(Q):
+        return float(kinetic_energy(rollout(Q, None, s, dts)[0], s))
+    for _ in range(3):
+        v = torch.tensor(rng.standard_normal(Q0.shape)) * 0.1
+        eps = 1e-6
+        fd = (ke(Q0 + eps * v) - ke(Q0 - eps * v)) / (2 * eps)
+        an = float((g * v).sum())
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-12
