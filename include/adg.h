@@ -189,6 +189,30 @@ adg_status adg_fused_end(adg_ctx* ctx);
 adg_status adg_step_adjoint(adg_ctx* ctx, const double* d_Qn, const double* d_params,
                             const double* d_dt, double* d_Qbar, double* d_params_bar);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): adg_step
+ * (predict + correct, the same kernels and results) with the face hull and the
+ * per-block maxima in a static device array of the library instead of a
+ * caller workspace.  The array holds at most 32 MiB (33554432 bytes) per GPU
+ * and stays allocated on every GPU the library ran on until the process ends.
+ *   ctx           created by adg_init(cfg, NULL, 0, stream, &ctx): a context
+ *                 without workspace; adg_init looks up the array's address on
+ *                 the current device and returns ADG_ERR_WORKSPACE when
+ *                 adg_query's workspace_bytes for cfg exceeds 32 MiB, and
+ *                 ADG_ERR_INVALID_ARG when cfg->adjoint or cfg->fused is set;
+ *   d_Q, d_params, d_dt, d_flag   as for adg_step;
+ *   d_lambda_max  (nullable) out: the largest directional wave speed of the
+ *                 new state (the input of calcTimeStep).
+ * Calls no hipMalloc, hipFree or other allocating routine.  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (other
+ * streams, other threads, other contexts) race on it.  The array keeps the
+ * last call's contents; every value a call reads was written by the same
+ * call.  On a context without workspace every other stepping entry point
+ * returns ADG_ERR_WORKSPACE, and adg_step_noalloc on a context with a
+ * workspace does too. */
+adg_status adg_step_noalloc(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt,
+                            int32_t* d_flag, double* d_lambda_max);
+
 /* Free a context (host memory only). */
 adg_status adg_destroy(adg_ctx* ctx);
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/adg.h"
@@ -129,6 +130,37 @@ Layout layout_of(const adg_config* c, const adg::Launchers* L) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// Scratch of adg_step_noalloc: the face hull and the per-block maxima of one
+// step, in a file-scope device array (one copy per GPU, held until the process
+// ends).  Host code never passes `scratch` itself to a kernel: its device
+// address on the current GPU comes from hipGetSymbolAddress, taken once per
+// device by adg_init and kept in g_scratch_ptr.
+constexpr int64_t kStaticScratchBytes = int64_t(32) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) static double scratch[kStaticScratchBytes / 8];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+adg_status static_scratch(void** out, std::string* msg) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) { *msg = std::string("hipGetDevice: ") + hipGetErrorString(e); return ADG_ERR_DEVICE; }
+  if (dev < 0 || dev >= kMaxDevices) { *msg = "device index out of range"; return ADG_ERR_DEVICE; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return ADG_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ADG_OK;
+}
+
 // First stage of the global maximum: 256 blocks, one maximum each.
 __global__ void __launch_bounds__(256) k_max256(const double* partial, int64_t cnt, double* out) {
   __shared__ double red[4];
@@ -219,6 +251,7 @@ struct adg_ctx {
   adg::HostTables tab;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
+  bool static_ws = false;       // ws is the static scratch: only adg_step_noalloc may run
   Layout lay;
   int64_t n_partial_used = 0;
   int64_t ncells = 0;
@@ -309,9 +342,26 @@ adg_status adg_init(const adg_config* cfg, void* d_workspace, int64_t workspace_
   int64_t need = 0;
   adg_status s = adg_query(cfg, nullptr, nullptr, &need);
   if (s != ADG_OK) return s;
-  if (!d_workspace) { g_err = "workspace is NULL"; return ADG_ERR_INVALID_ARG; }
-  if (!aligned16(d_workspace)) { g_err = "workspace not 16-byte aligned"; return ADG_ERR_INVALID_ARG; }
-  if (workspace_bytes < need) { g_err = "workspace too small"; return ADG_ERR_WORKSPACE; }
+  void* sp = nullptr;
+  const bool static_ws = !d_workspace && workspace_bytes == 0;
+  if (static_ws) {
+    // context for adg_step_noalloc: the library's static scratch replaces the workspace
+    if (cfg->adjoint || cfg->fused) {
+      g_err = "a context without workspace (adg_step_noalloc) needs adjoint = 0 and fused = 0";
+      return ADG_ERR_INVALID_ARG;
+    }
+    if (need > kStaticScratchBytes) {
+      g_err = "adg_step_noalloc: this grid needs " + std::to_string(need) +
+              " bytes of scratch, the static maximum is " + std::to_string(kStaticScratchBytes);
+      return ADG_ERR_WORKSPACE;
+    }
+    std::string msg;
+    if ((s = static_scratch(&sp, &msg)) != ADG_OK) { g_err = msg; return s; }
+  } else {
+    if (!d_workspace) { g_err = "workspace is NULL"; return ADG_ERR_INVALID_ARG; }
+    if (!aligned16(d_workspace)) { g_err = "workspace not 16-byte aligned"; return ADG_ERR_INVALID_ARG; }
+    if (workspace_bytes < need) { g_err = "workspace too small"; return ADG_ERR_WORKSPACE; }
+  }
   adg_ctx* c = new adg_ctx();
   c->cfg = *cfg;
   c->L = find(cfg);
@@ -321,7 +371,8 @@ adg_status adg_init(const adg_config* cfg, void* d_workspace, int64_t workspace_
     return ADG_ERR_INVALID_ARG;
   }
   c->stream = reinterpret_cast<hipStream_t>(stream);
-  c->ws = reinterpret_cast<char*>(d_workspace);
+  c->ws = reinterpret_cast<char*>(static_ws ? sp : d_workspace);
+  c->static_ws = static_ws;
   c->lay = layout_of(cfg, c->L);
   c->ncells = n_cells_of(cfg);
   c->h = cfg->length[0] / cfg->n_cells[0];
@@ -344,8 +395,12 @@ adg_status adg_destroy(adg_ctx* ctx) {
   return ADG_OK;
 }
 
-static adg_status check_state(adg_ctx* ctx, const void* Q, const void* params, const void* dt) {
+static adg_status check_state(adg_ctx* ctx, const void* Q, const void* params, const void* dt,
+                              bool noalloc = false) {
   if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (ctx->static_ws != noalloc)
+    return ctx->fail(ADG_ERR_WORKSPACE, noalloc ? "adg_step_noalloc needs a context created without workspace"
+                                                : "context has no workspace: only adg_step_noalloc runs on it");
   if (!Q || !dt) return ctx->fail(ADG_ERR_INVALID_ARG, "Q and dt are required");
   if (n_params(ctx->cfg.pde) > 0 && !params)
     return ctx->fail(ADG_ERR_INVALID_ARG, "this PDE needs per-cell params");
@@ -407,6 +462,8 @@ static void stage_partial(adg_ctx* ctx, const double** part, int64_t* cnt) {
 
 adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_dt) {
   if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (ctx->static_ws)
+    return ctx->fail(ADG_ERR_WORKSPACE, "context has no workspace: only adg_step_noalloc runs on it");
   if (!(cfl > 0.0)) return ctx->fail(ADG_ERR_INVALID_ARG, "cfl must be positive");
   if (!d_lambda_max && !d_dt) return ctx->fail(ADG_ERR_INVALID_ARG, "no output");
   if (ctx->n_partial_used <= 0)
@@ -417,6 +474,30 @@ adg_status adg_cfl_dt(adg_ctx* ctx, double cfl, double* d_lambda_max, double* d_
   stage_partial(ctx, &part, &cnt);
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, part, cnt, coef, d_lambda_max, d_dt);
   return ctx->launched((int)hipGetLastError(), "cfl_dt");
+}
+
+adg_status adg_step_noalloc(adg_ctx* ctx, double* d_Q, const double* d_params, const double* d_dt,
+                            int32_t* d_flag, double* d_lambda_max) {
+  adg_status s = check_state(ctx, d_Q, d_params, d_dt, true);
+  if (s != ADG_OK) return s;
+  if (ctx->lay.total > kStaticScratchBytes)     // adg_init checked it too
+    return ctx->fail(ADG_ERR_WORKSPACE, "adg_step_noalloc: grid exceeds the static scratch");
+  adg::LaunchArgs a = ctx->args();
+  a.Q = d_Q;
+  a.params = d_params;
+  a.dt = d_dt;
+  if ((s = ctx->launched(ctx->L->predict(a), "noalloc: predict")) != ADG_OK) return s;
+  a.flag = d_flag;
+  if ((s = ctx->launched(ctx->L->correct(a), "noalloc: correct")) != ADG_OK) return s;
+  if (d_lambda_max) {
+    const double* part = nullptr;
+    int64_t cnt = 0;
+    stage_partial(ctx, &part, &cnt);
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, ctx->stream, part, cnt, 1.0, d_lambda_max,
+                       static_cast<double*>(nullptr));
+    return ctx->launched((int)hipGetLastError(), "noalloc: lambda_max");
+  }
+  return ADG_OK;
 }
 
 static void fz_dt(adg_ctx* ctx, int mode) {

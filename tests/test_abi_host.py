@@ -98,13 +98,22 @@ def test_query_rejects_nonuniform_h_and_bad_cells(L):
 def test_init_rejects_bad_workspace_without_touching_device(L):
     c = cfg_of(inputs.preset("C1"))
     ctx = ctypes.c_void_p()
-    assert L.adg_init(ctypes.byref(c), None, 0, None, ctypes.byref(ctx)) == _lib.ADG_ERR_INVALID_ARG
+    assert L.adg_init(ctypes.byref(c), None, 1 << 20, None, ctypes.byref(ctx)) == \
+        _lib.ADG_ERR_INVALID_ARG
+    # no workspace at all asks for adg_step_noalloc's static scratch, which
+    # holds at most 32 MiB: the C2 hull (6.4 GB) is refused before any device call
+    c2 = cfg_of(inputs.preset("C2"))
+    assert L.adg_init(ctypes.byref(c2), None, 0, None, ctypes.byref(ctx)) == _lib.ADG_ERR_WORKSPACE
+    assert "static maximum" in L.adg_last_error(None).decode()
+    c2.fused = 1
+    assert L.adg_init(ctypes.byref(c2), None, 0, None, ctypes.byref(ctx)) == _lib.ADG_ERR_INVALID_ARG
     assert L.adg_init(ctypes.byref(c), ctypes.c_void_p(16), 10, None,
                       ctypes.byref(ctx)) == _lib.ADG_ERR_WORKSPACE
     assert L.adg_init(ctypes.byref(c), ctypes.c_void_p(8), 1 << 30, None,
                       ctypes.byref(ctx)) == _lib.ADG_ERR_INVALID_ARG   # misaligned
     assert L.adg_step(None, None, None, None, None) == _lib.ADG_ERR_INVALID_ARG
     assert L.adg_cfl_dt(None, 0.9, None, None) == _lib.ADG_ERR_INVALID_ARG
+    assert L.adg_step_noalloc(None, None, None, None, None, None) == _lib.ADG_ERR_INVALID_ARG
 
 
 def test_product_path_has_no_oracle_dependency():
