@@ -83,21 +83,26 @@ def test_fused_float_predictor_tracks_plain_float_path():
     Q, used, reruns, flag = _gpu_fused(wl, Q0, None, 4, 0.5, 0.99)
     QP = _plain(wl, Q0, None, used).cpu()
     assert flag == 0
-    # both are float predictors; the fused and plain kernels contract their
-    # float arithmetic differently, so they agree to float rounding times dt
-    assert float((Q - QP).abs().max()) < 1e-8 * float(QP.abs().max())
+    # both are float predictors whose kernels order (and contract to FMA)
+    # their float arithmetic differently: per step they may differ by the
+    # float rounding bound of the update, 8 u max|Q| with u = 2^-24 (the
+    # derivation is in tests/test_gpu_precision.py)
+    assert float((Q - QP).abs().max()) < 4 * 8 * 2.0 ** -24 * float(QP.abs().max())
 
 
-def test_fused_full_size_c2_matches_plain_steps():
+@pytest.mark.parametrize("ic,steps", [("bump", 3), ("fourier", 10)])
+def test_fused_full_size_c2_matches_plain_steps(ic, steps):
     """The benchmark's workload and launch configuration (81^3 cells, N = 4):
-    three fused steps equal three plain steps with the same dts."""
-    wl = inputs.preset("C2")
+    fused steps equal plain steps with the same dts, on the bump (a
+    stationary contact) and on a moving flow (Fourier density modes with
+    p = rho^gamma, every field changing)."""
+    wl = inputs.preset("C2").with_(extra={"ic": ic})
     Q0 = torch.tensor(inputs.initial_state(wl), device="cuda")
-    print("fused C2 full size", flush=True)
+    print("fused C2 full size", ic, steps, flush=True)
     from paper_1801_08682_amd.stepper import Stepper
     st = Stepper(wl, fused=True)
     Q = Q0.clone()
-    used, reruns = st.run_fused(Q, None, 3, wl.cfl, 0.99)
+    used, reruns = st.run_fused(Q, None, steps, wl.cfl, 0.99)
     torch.cuda.synchronize()
     st.close()
     QP = _plain(wl, Q0, None, used.cpu().numpy())
