@@ -54,6 +54,30 @@ def pred_flops_per_cell(d, n, m, R, cF):
     return R * pic + fin
 
 
+def corr_flops_per_cell(d, n, m):
+    """Algorithmic flops of the corrector per cell: Rusanov on the 2d faces
+    (n^(d-1) nodes, about 5m + 15 flops each incl. the wave speeds), the
+    face lift, the update and the wave speeds of the new state."""
+    return 2 * d * n ** (d - 1) * (5 * m + 15) + 4 * d * m * n ** d + 2 * m * n ** d + 15 * n ** d
+
+
+def step_flops_per_cell(d, n, m, R, cF=30):
+    """Algorithmic flops of one whole step per cell: predictor + corrector
+    (c_F = 30 flops for the three 3D Euler fluxes at a node)."""
+    return pred_flops_per_cell(d, n, m, R, cF) + corr_flops_per_cell(d, n, m)
+
+
+def cpu_model():
+    """The host CPU's model name (as lscpu prints it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def corr_bytes_per_cell(d, n, m, real_bytes):
     """Algorithmic HBM bytes of one adg_correct per cell: read Q~ and write Q
     (2 m n^d float64) and read the face hull once (2d faces x 2 quantities x
@@ -99,7 +123,7 @@ def cpu_baseline(args):
             "unit": "DoF-updates/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"{k}^3-cell periodic grid of the same workload (Euler N=4, "
                       f"h=1/81, bump), {args.cpu_steps} steps after 1 warm-up, "
-                      f"torch CPU float64 on {platform.processor() or 'host'}"}
+                      f"torch CPU float64", "cpu_model": cpu_model()}
 
 
 def adjoint_bench(args):
@@ -161,7 +185,15 @@ def other_workload(args, torch):
     par = inputs.cell_params(wl, seed=0)
     par = None if par is None else torch.tensor(par, device="cuda")
     res, states = {}, {}
-    for prec in (inputs.FP64, inputs.FP32):
+    from paper_1801_08682_amd import _lib
+    precs = [inputs.FP64, inputs.FP32]
+    try:
+        _lib.query(_lib.make_config(wl.dim, wl.order, wl.n_cells, [wl.length] * wl.dim, wl.pde,
+                                    wl.pde_param, precision=inputs.BF16))
+        precs.append(inputs.BF16)
+    except _lib.AdgError:
+        pass
+    for prec in precs:
         st = Stepper(wl.with_(precision=prec))
         if wl.adaptive_dt:
             lam = None
@@ -189,17 +221,24 @@ def other_workload(args, torch):
     W = w
     for _ in range(wl.dim - 1):
         W = torch.kron(w, W)
-    ref, got = states[inputs.FP64], states[inputs.FP32]
+    ref = states[inputs.FP64]
     norms = [float(torch.sqrt((W * ref[..., v] ** 2).sum())) for v in range(wl.m)]
-    err = []
-    for v in range(wl.m):
-        e = float(torch.sqrt((W * (got[..., v] - ref[..., v]) ** 2).sum()))
-        err.append(e / norms[v] if norms[v] > 1e-8 * max(norms) else e)
-    return {"metric": "DoF-updates/s", "unit": "DoF-updates/s", "workload": wl.name,
-            "config": {"pde": wl.pde, "dim": wl.dim, "order": wl.order, "cells": wl.ncells,
-                       "steps": steps, "cfl": wl.cfl},
-            "fp64": res[inputs.FP64], "fp32_predictor": res[inputs.FP32],
-            "fp32_rel_l2_vs_fp64_per_field": err}
+
+    def errs(got):
+        err = []
+        for v in range(wl.m):
+            e = float(torch.sqrt((W * (got[..., v] - ref[..., v]) ** 2).sum()))
+            err.append(e / norms[v] if norms[v] > 1e-8 * max(norms) else e)
+        return err
+    out = {"metric": "DoF-updates/s", "unit": "DoF-updates/s", "workload": wl.name,
+           "config": {"pde": wl.pde, "dim": wl.dim, "order": wl.order, "cells": wl.ncells,
+                      "steps": steps, "cfl": wl.cfl},
+           "fp64": res[inputs.FP64], "fp32_predictor": res[inputs.FP32],
+           "fp32_rel_l2_vs_fp64_per_field": errs(states[inputs.FP32])}
+    if inputs.BF16 in res:
+        out["bf16_predictor"] = res[inputs.BF16]
+        out["bf16_rel_l2_vs_fp64_per_field"] = errs(states[inputs.BF16])
+    return out
 
 
 def run_path(st, Q0, steps, warmup, cfl, torch):
@@ -341,6 +380,7 @@ def main():
     dofs = wl.ncells * wl.dofs_per_cell
     R = wl.order + 1
     fpc = pred_flops_per_cell(d, n, m, R, 30)
+    fsc = step_flops_per_cell(d, n, m, R, 30)
     hull = 2 * d * 2 * m * n ** (d - 1)                      # hull doubles per cell
     full = args.cells == 81
     st = Stepper(wl, fused=True)
@@ -351,7 +391,7 @@ def main():
     _, wall2, pred, corr, dtk = run_path(st, Q0, args.steps, args.warmup, wl.cfl, torch)
     st.close()
     del st
-    achieved = fpc * wl.ncells / (sweep * 1e-3) / 1e12
+    achieved = fsc * wl.ncells / (sweep * 1e-3) / 1e12
     pred_achieved = fpc * wl.ncells / (pred * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": dofs * args.steps / wall, "unit": "DoF-updates/s",
@@ -381,11 +421,12 @@ def main():
                      "traffic": measured_traffic("k_fused_fp64") if full else None,
                      "traffic_unit": "bytes per launch",
                      "algorithmic_bytes": wl.ncells * (2 * wl.dofs_per_cell * 8 + 2 * hull * 8),
-                     "flops_per_cell": fpc,
-                     "note": "achieved counts the predictor's algorithmic flops only (the "
-                             "corrector's few percent are left out) over the whole sweep's "
-                             "event time (k_fused plus the dt reduction and the skipped "
-                             "rerun launch)"},
+                     "flops_per_cell": fsc,
+                     "note": "achieved = algorithmic flops of the whole step per cell "
+                             "(sum-factorised predictor with R = N+1 Picard iterations, "
+                             "c_F = 30 flops for the three fluxes at a node, plus the "
+                             "corrector) x cells / the sweep's event time (k_fused plus the "
+                             "dt reduction and the skipped rerun launch)"},
         "two_kernel": {
             "stepping": "Alg. 1: adg_predict, adg_correct, adg_cfl_dt per step, dt = 0.5625 "
                         "h/(3 (2N+1) lambda_max)",
@@ -403,44 +444,7 @@ def main():
                             "traffic": measured_traffic("k_corr_fp64") if full else None}},
     }
     if not args.no_mixed:
-        print("[bench] fp32-predictor runs", file=sys.stderr, flush=True)
-        st32 = Stepper(wl.with_(precision=inputs.FP32), fused=True)
-        Q32, wall32, sweep32, reruns32, _ = run_fused_path(st32, Q0, args.steps, args.warmup,
-                                                           wl.cfl, C_DT, torch)
-        _, wall32b, pred32, corr32, dtk32 = run_path(st32, Q0, args.steps, args.warmup,
-                                                     wl.cfl, torch)
-        W = torch.tensor(np.kron(np.kron(st32_w(n), st32_w(n)), st32_w(n)), device="cuda")
-        err = field_errors(Q32, Q64, W, m, torch)
-        # the bump is a stationary contact (u = 0, uniform p), which a predictor
-        # that differentiates constants exactly keeps almost unchanged; the
-        # float predictor's accuracy on a moving flow is measured on Fourier
-        # density modes with p = rho^gamma (acoustic waves) on the same grid
-        print("[bench] fp32 vs fp64 on a moving flow", file=sys.stderr, flush=True)
-        wlf = wl.with_(extra={"ic": "fourier"})
-        Qf = torch.tensor(inputs.initial_state(wlf), device="cuda")
-        moving = {}
-        for prec in (inputs.FP64, inputs.FP32):
-            stf = Stepper(wlf.with_(precision=prec), fused=True)
-            moving[prec] = run_fused_path(stf, Qf, args.steps, 0, wl.cfl, C_DT, torch)[0]
-            stf.close()
-        err_moving = field_errors(moving[inputs.FP32], moving[inputs.FP64], W, m, torch)
-        del moving, Qf
-        out["mixed"] = {"precision": "fp32 predictor, fp64 corrector",
-                        "value": dofs * args.steps / wall32, "ms_per_step": wall32 * 1e3 / args.steps,
-                        "kernel_ms": {"sweep": sweep32}, "reruns": reruns32,
-                        "two_kernel": {"value": dofs * args.steps / wall32b,
-                                       "ms_per_step": wall32b * 1e3 / args.steps,
-                                       "kernel_ms": {"predict": pred32, "correct": corr32,
-                                                     "cfl_dt": dtk32}},
-                        "rel_l2_vs_fp64_per_field": err,
-                        "rel_l2_vs_fp64_per_field_moving_flow": err_moving,
-                        "l2_note": f"after {args.steps} fused steps of each path, against the "
-                                   "float64 GPU path (parity-checked against the oracle); "
-                                   "absolute L2 for fields with negligible norm (momentum); "
-                                   "the headline state is a stationary contact, the moving "
-                                   "flow is 8 random Fourier density modes with p = rho^gamma "
-                                   "on the same grid (seed 0)"}
-        st32.close()
+        out.update(mixed_paths(args, wl, Q0, dofs, torch))
     if not args.no_adjoint:
         print("[bench] adjoint (C4 misfit gradient)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_bench(args)
@@ -457,6 +461,67 @@ def main():
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
+
+
+ACC_STEPS = 100     # the metric states the reduced-precision error at step 100
+
+
+def mixed_paths(args, wl, Q0, dofs, torch):
+    """The reduced-precision predictors (float: float32 Picard iteration;
+    bf16: float32 with the pencil contractions on the matrix cores, inputs
+    rounded to bfloat16, float32 accumulation) with the float64 corrector:
+    timed like the float64 path, and their per-field relative L2 difference
+    to the float64 path after ACC_STEPS fused steps (untimed, whatever
+    --steps is), on the headline state and on a moving flow."""
+    from paper_1801_08682_amd import inputs
+    from paper_1801_08682_amd.stepper import Stepper
+    n, m = wl.n, wl.m
+    W = torch.tensor(np.kron(np.kron(st32_w(n), st32_w(n)), st32_w(n)), device="cuda")
+    wlf = wl.with_(extra={"ic": "fourier"})
+    Qf = torch.tensor(inputs.initial_state(wlf), device="cuda")
+    inits = {"bump": Q0, "moving_flow": Qf}
+
+    def run100(prec, Qi):
+        st = Stepper(wl.with_(precision=prec), fused=True)
+        Q = Qi.clone()
+        st.run_fused(Q, None, ACC_STEPS, wl.cfl, C_DT)
+        torch.cuda.synchronize()
+        st.close()
+        return Q
+
+    print("[bench] float64 reference states at step 100", file=sys.stderr, flush=True)
+    ref = {k: run100(inputs.FP64, Qi) for k, Qi in inits.items()}
+    res = {}
+    for prec, key, desc in ((inputs.FP32, "mixed", "fp32 predictor, fp64 corrector"),
+                            (inputs.BF16, "mixed_bf16",
+                             "bf16-input matrix-core contractions with fp32 accumulation in "
+                             "an fp32 predictor, fp64 corrector")):
+        print(f"[bench] {key} runs", file=sys.stderr, flush=True)
+        st = Stepper(wl.with_(precision=prec), fused=True)
+        _, wall, sweep, reruns, _ = run_fused_path(st, Q0, args.steps, args.warmup, wl.cfl,
+                                                   C_DT, torch)
+        _, wallb, pred, corr, dtk = run_path(st, Q0, args.steps, args.warmup, wl.cfl, torch)
+        st.close()
+        errs = {k: field_errors(run100(prec, Qi), ref[k], W, m, torch) for k, Qi in inits.items()}
+        res[key] = {"precision": desc,
+                    "value": dofs * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
+                    "kernel_ms": {"sweep": sweep}, "reruns": reruns,
+                    "two_kernel": {"value": dofs * args.steps / wallb,
+                                   "ms_per_step": wallb * 1e3 / args.steps,
+                                   "kernel_ms": {"predict": pred, "correct": corr,
+                                                 "cfl_dt": dtk}},
+                    "rel_l2_vs_fp64_per_field": errs["bump"],
+                    "rel_l2_vs_fp64_per_field_moving_flow": errs["moving_flow"],
+                    "l2_step": ACC_STEPS,
+                    "l2_note": f"per-field relative L2 (Gauss-Legendre weights) after "
+                               f"{ACC_STEPS} fused steps of each path against the float64 GPU "
+                               "path (itself checked against the oracle step by step on this "
+                               "grid); absolute L2 for fields with negligible norm (momentum "
+                               "of the bump); the bump is a stationary contact, the moving "
+                               "flow is 8 seeded Fourier density modes with p = rho^gamma on "
+                               "the same grid"}
+    del ref, inits, Qf
+    return res
 
 
 def copy_calibration(args, torch):

@@ -61,7 +61,13 @@ typedef enum { ADG_ADVECTION = 0, ADG_EULER = 1, ADG_ELASTIC = 2, ADG_ACOUSTIC =
 
 /* Arithmetic of the predictor (predict + extrapolate).  The volume
  * integration, Riemann solve, face integration and update always run in
- * float64.  FP32: float Picard iteration and float face traces. */
+ * float64.  FP32: float Picard iteration and float face traces.  BF16: as
+ * FP32, but every pencil contraction with D of the Picard iteration takes
+ * bfloat16 inputs (the flux differences to the pencil's reference flux,
+ * rounded to nearest even; D as the pair Dh + Dl of two bfloat16 values) and
+ * accumulates in float32 on the matrix cores (v_mfma_f32_16x16x32_bf16);
+ * compiled for 3D Euler N = 3, 4, 7, 3D elasticity N = 5 and 3D acoustics
+ * N = 3 (other combinations return ADG_ERR_UNSUPPORTED). */
 typedef enum { ADG_FP64 = 0, ADG_FP32 = 1, ADG_BF16 = 2 } adg_precision;
 
 typedef struct {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <type_traits>
 
 #include "pde.hpp"
@@ -58,7 +59,25 @@ struct KTab {
   // odd n the middle column Cm[k] = D[k][n/2] and middle row Dm[j] = D[n/2][j].
   static constexpr int H = n / 2 > 0 ? n / 2 : 1;
   Real Ce[H][H], Co[H][H], Cm[H], Dm[H];
+  // bfloat16 pair of D for the matrix-core contraction: Dh = bf16(fl32(D)),
+  // Dl = bf16(fl32(D - Dh)), both round to nearest even (bit patterns); their
+  // sum is a 16-bit-significand operator that float32 holds exactly.
+  uint16_t Dh[n][n], Dl[n][n];
 };
+
+// float -> bfloat16 bit pattern, round to nearest, ties to even (finite x).
+inline uint16_t bf16_bits_rne(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+inline double bf16_bits_value(uint16_t h) {
+  const uint32_t b = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return (double)f;
+}
 
 template <int n, class Real>
 inline KTab<n, Real> make_ktab(const HostTables& h) {
@@ -86,7 +105,89 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
     t.Cm[k] = (Real)h.D[k * n + n / 2];
     t.Dm[k] = (Real)h.D[(n / 2) * n + k];
   }
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j) {
+      const double d = h.D[k * n + j];
+      t.Dh[k][j] = bf16_bits_rne((float)d);
+      t.Dl[k][j] = bf16_bits_rne((float)(d - bf16_bits_value(t.Dh[k][j])));
+    }
   return t;
+}
+
+// Matrix-core contraction of a pencil (gfx950 v_mfma_f32_16x16x32_bf16).
+// Operand layout of that instruction (verified on the device): lane l holds
+// A[l % 16][8 (l / 16) + r] and B[8 (l / 16) + r][l % 16] in its register r
+// (r < 8) and receives C[4 (l / 16) + i][l % 16] (i < 4).  With A block
+// diagonal, A[4 g + i][8 g + j] = Dsel[4 h + i][j] for lane group g = l / 16,
+// each lane's 8 B values (its own pencil's inputs x_j, j < n) produce
+// sum_j Dsel[4 h + i][j] x_j, i < 4, in its own C: a per-lane contraction of
+// four output nodes (h = 0: nodes 0..3, h = 1: nodes 4..7).  Every lane of
+// the wave takes part; lanes without a task must hold finite inputs.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int n>
+struct MxOps {
+  static constexpr int NH = n > 4 ? 2 : 1;          // output halves
+  bf16x8 hi[NH], lo[NH];
+};
+
+template <int n, class Tab>
+__device__ __forceinline__ MxOps<n> make_mx_ops(const Tab& t) {
+  static_assert(n <= 8, "the matrix-core contraction takes at most 8 nodes per pencil");
+  MxOps<n> o;
+  const int l = (int)(threadIdx.x & 63);
+  const int m = l & 15, g = l >> 4;
+  const bool mine = (m >> 2) == g;
+#pragma unroll
+  for (int h = 0; h < MxOps<n>::NH; ++h) {
+    const int row = 4 * h + (m & 3);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const bool on = mine && row < n && r < n;
+      const uint16_t bh = on ? t.Dh[row < n ? row : 0][r < n ? r : 0] : (uint16_t)0;
+      const uint16_t bl = on ? t.Dl[row < n ? row : 0][r < n ? r : 0] : (uint16_t)0;
+      o.hi[h][r] = __builtin_bit_cast(__bf16, bh);
+      o.lo[h][r] = __builtin_bit_cast(__bf16, bl);
+    }
+  }
+  return o;
+}
+
+// The reference flux of a pencil: the first node for n < 5, the middle node
+// for odd n, the mean of the middle pair for even n (computed in float as
+// 0.5 (a + b)).
+template <int n, int M>
+__device__ __forceinline__ float pencil_ref(const float (&F)[n][M], int v) {
+  if constexpr (n < 5) return F[0][v];
+  else if constexpr (n % 2 == 1) return F[n / 2][v];
+  else return 0.5f * (F[n / 2 - 1][v] + F[n / 2][v]);
+}
+
+// out[k][v] = sum_j D[k][j] x_j[v] with x_j = bf16(F_j - F_ref) (round to
+// nearest even) and D = Dh + Dl, float32 accumulation on the matrix cores.
+template <int n, int M, class FluxAt>
+__device__ __forceinline__ void pencil_dF_mx(const MxOps<n>& A, FluxAt&& flux_at,
+                                             float (&out)[n][M]) {
+  float F[n][M];
+#pragma unroll
+  for (int j = 0; j < n; ++j) flux_at(j, F[j]);
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const float Fr = pencil_ref<n, M>(F, v);
+    bf16x8 B;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) B[r] = r < n ? (__bf16)(F[r < n ? r : 0][v] - Fr) : (__bf16)0.0f;
+#pragma unroll
+    for (int h = 0; h < MxOps<n>::NH; ++h) {
+      floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[h], B, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[h], B, c, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * h + i < n) out[4 * h + i][v] = c[i];
+    }
+  }
 }
 
 // One pencil's contraction out[k][v] = sum_j D[k][j] F_j[v], F_j from

@@ -26,10 +26,14 @@ namespace adg {
 // ST_: the hull keeps the traces at every time node (Table 1's extrapolate
 // cardinality) and the Riemann problems are solved per time node; otherwise
 // the traces are time-integrated (one time value per face node).
-template <int D_, int N_, template <int> class PDET, class Real_, bool ST_ = false>
+// MX_: the bfloat16 predictor (float arithmetic, the Picard contractions on
+// the matrix cores with bfloat16 inputs; Real_ must be float).
+template <int D_, int N_, template <int> class PDET, class Real_, bool ST_ = false,
+          bool MX_ = false>
 struct Fwd {
   static constexpr int D = D_, N = N_, n = N_ + 1;
   static constexpr bool ST = ST_;
+  static constexpr bool MX = MX_;
   static constexpr int NT = ST_ ? N_ + 1 : 1;         // time values per trace
   using PDE = PDET<D_>;
   using Real = Real_;
@@ -38,7 +42,14 @@ struct Fwd {
   static constexpr int NQ = PDE::LINEAR ? 1 : 2;
   // predictor block
   static constexpr int CPB = (NS >= 128) ? 1 : 128 / NS;
-  static constexpr int THREADS = CPB * NS;
+  static constexpr int NODE_THREADS = CPB * NS;      // one thread per spatial node
+  // Threads per cell: one per node; the matrix-core contraction takes every
+  // lane of a wave, so a cell gets whole waves (the threads past the nodes
+  // only take pencil tasks).
+  static constexpr int TPC = (MX_ && CPB == 1) ? (NS + 63) / 64 * 64 : NS;
+  static constexpr int THREADS = CPB * TPC;
+  static_assert(!MX_ || (THREADS % 64 == 0 && std::is_same<Real_, float>::value && !ST_),
+                "the matrix-core predictor needs whole waves and float arithmetic");
   // LDS slice layout, as planes indexed by the slot e = tt * NSP + node of a
   // buffer of NSL time slices.  Packed: the variables in groups of VEC
   // (2 float64, 4 float) in 16-byte planes [group][slice][node] and the
@@ -124,8 +135,8 @@ struct Fwd {
   static constexpr int CORR_CELL_BYTES = (2 * D * NF * (M + NT) + 2 * D * NT) * 8;
 };
 
-template <int D_, int N_, template <int> class PDET, class Real_, bool ST_>
-__device__ __forceinline__ int Fwd<D_, N_, PDET, Real_, ST_>::lidx(int tt, int v, int pos) {
+template <int D_, int N_, template <int> class PDET, class Real_, bool ST_, bool MX_>
+__device__ __forceinline__ int Fwd<D_, N_, PDET, Real_, ST_, MX_>::lidx(int tt, int v, int pos) {
   return lidx_e<S>(tt * NSP + slot(pos), v);
 }
 
@@ -220,7 +231,14 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   for (int t = 0; t < n; ++t)
 #pragma unroll
     for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v];
-  const int pa = a;
+  // Node role (publish, time operator, finalisation) on the first NS
+  // threads of the cell; threads past them (whole waves for the matrix
+  // cores) only take pencil tasks.
+  const bool node = (K::TPC == NS) || a < NS;
+  const int pa = node ? a : 0;
+  // Matrix-core operands of this lane (bfloat16 predictor).
+  [[maybe_unused]] MxOps<n> mx;
+  if constexpr (K::MX) mx = make_mx_ops<n>(p.t);
   // First slot of this lane's pencil task for each batch size used and axis.
   constexpr int TAIL = n - (K::NB - 1) * S;
   int ordF[D], ordS[D], ordT[D];
@@ -241,6 +259,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   // the PDE's publish form.
   auto publish = [&](auto T0_, auto NS_) {
     constexpr int t0 = decltype(T0_)::value, ns = decltype(NS_)::value;
+    if (!node) return;
 #pragma unroll
     for (int tt = 0; tt < ns; ++tt) {
       Real w[M];
@@ -256,14 +275,17 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
       constexpr int sI = K::sstride(I);
-      auto pencil = [&](int e0) {
+      auto pencil = [&](int e0, bool wr) {
         Real out[n][M];
-        pencil_dF<n, M, Real>(p.t, [&](int j, Real (&F)[M]) {
+        auto flux_at = [&](int j, Real (&F)[M]) {
           Real qn[M];
 #pragma unroll
           for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e0 + j * sI, v)];
           PDE::template flux_pub<I>(qn, F, p.g, cp);
-        }, out);
+        };
+        if constexpr (K::MX) pencil_dF_mx<n, M>(mx, flux_at, out);
+        else pencil_dF<n, M, Real>(p.t, flux_at, out);
+        if (!wr) return;
         // axis sums: for small pencils every read before any write, so the
         // reads are not serialised behind possibly aliasing stores; large
         // ones node by node (fewer live registers)
@@ -281,7 +303,13 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
             Rs[K::template lidx_e<S>(e0 + k * sI, v)] = out[k][v];
           }
       };
-      if (ns * NF == NS || a < ns * NF) pencil(e0_of(NS_, I_));   // at most one task per thread
+      if constexpr (K::MX) {
+        // every lane takes part in the matrix-core contraction; lanes
+        // without a task contract a valid pencil and discard it
+        pencil(e0_of(NS_, I_), a < ns * NF);
+      } else if (ns * NF == NS || a < ns * NF) {
+        pencil(e0_of(NS_, I_), true);             // at most one task per thread
+      }
       __syncthreads();
     });
   };
@@ -296,7 +324,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     Real* Fs = reinterpret_cast<Real*>(base);      // [axis][var][node] planes
     constexpr bool REF = !std::is_same<Real, double>::value;
     Real Fo[REF ? D : 1][M];
-    {
+    if (node) {
       Real uu[M], w[M];
 #pragma unroll
       for (int v = 0; v < M; ++v) uu[v] = (Real)u[v];
@@ -307,7 +335,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         PDE::template flux_pub<I>(w, F, p.g, cp);
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          Fs[K::template lidx_e<D>(I * NSP + K::slot(a), v)] = F[v];
+          Fs[K::template lidx_e<D>(I * NSP + K::slot(pa), v)] = F[v];
           if constexpr (REF) Fo[I][v] = F[v];
         }
       });
@@ -316,21 +344,42 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     Real rv[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) rv[v] = Real(0);
-    static_for<0, D>([&](auto I_) {
+    if (node) static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
       constexpr int sI = K::sstride(I);
-      const int ai = coord<n, I>(a);
-      const int e0 = I * NSP + K::slot(a) - ai * sI;
+      const int ai = coord<n, I>(pa);
+      const int e0 = I * NSP + K::slot(pa) - ai * sI;
+      if constexpr (K::MX) {
+        // as the matrix-core pencils: x_j = bf16(F_j - F_ref) with the
+        // pencil's reference flux, contracted with Dh + Dl (exact in float)
+        float F[n][M];
 #pragma unroll
-      for (int j = 0; j < n; ++j) {
-        const Real dj = p.t.D[ai][j];
+        for (int j = 0; j < n; ++j)
+#pragma unroll
+          for (int v = 0; v < M; ++v) F[j][v] = Fs[K::template lidx_e<D>(e0 + j * sI, v)];
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          const Real F = Fs[K::template lidx_e<D>(e0 + j * sI, v)];
-          if constexpr (REF)
-            rv[v] = fma(dj, F - Fo[I][v], rv[v]);
-          else
-            rv[v] = fma(dj, F, rv[v]);
+          const float Fr = pencil_ref<n, M>(F, v);
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            const float dh = __builtin_bit_cast(float, (uint32_t)p.t.Dh[ai][j] << 16);
+            const float dl = __builtin_bit_cast(float, (uint32_t)p.t.Dl[ai][j] << 16);
+            const float x = (float)(__bf16)(F[j][v] - Fr);
+            rv[v] = fma(dh + dl, x, rv[v]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const Real dj = p.t.D[ai][j];
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            const Real F = Fs[K::template lidx_e<D>(e0 + j * sI, v)];
+            if constexpr (REF)
+              rv[v] = fma(dj, F - Fo[I][v], rv[v]);
+            else
+              rv[v] = fma(dj, F, rv[v]);
+          }
         }
       }
     });
@@ -347,19 +396,21 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     // pencil, contract with D, keep the result in registers.
     auto pencils = [&](auto NS_, auto& out) {
       constexpr int ns = decltype(NS_)::value;
-      const bool act = (ns * NF == NS) || a < ns * NF;
+      const bool act = (ns * NF == NS && K::TPC == NS) || a < ns * NF;
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         constexpr int sI = K::sstride(I);
         const int e0 = e0_of(NS_, I_);
-        if (act) {
-          pencil_dF<n, M, Real>(p.t, [&](int j, Real (&F)[M]) {
-            Real qn[M];
+        auto flux_at = [&](int j, Real (&F)[M]) {
+          Real qn[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e0 + j * sI, v)];
-            PDE::template flux_pub<I>(qn, F, p.g, cp);
-          }, out[I]);
-        }
+          for (int v = 0; v < M; ++v) qn[v] = Qs[K::template lidx_e<S>(e0 + j * sI, v)];
+          PDE::template flux_pub<I>(qn, F, p.g, cp);
+        };
+        // matrix cores: every lane takes part (lanes without a task
+        // contract a valid pencil and write nothing)
+        if constexpr (K::MX) pencil_dF_mx<n, M>(mx, flux_at, out[I]);
+        else if (act) pencil_dF<n, M, Real>(p.t, flux_at, out[I]);
       });
       __syncthreads();                              // all pencils read: reuse Qs as rhs
       static_for<0, D>([&](auto I_) {
@@ -396,7 +447,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       for (int v = 0; v < M; ++v) {
         Real rv[n];
 #pragma unroll
-        for (int tt = 0; tt < n; ++tt) rv[tt] = Qs[K::lidx(tt, v, pa)];
+        for (int tt = 0; tt < n; ++tt) rv[tt] = node ? Qs[K::lidx(tt, v, pa)] : Real(0);
 #pragma unroll
         for (int t = 0; t < n; ++t) {
           Real acc = Real(0);
@@ -444,7 +495,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   double* Fb = reinterpret_cast<double*>(base);   // [axis][var][node]: time-averaged F_i
   double* Qb = Fb + D * NS * M;                   // [var][node]: time-averaged q
   double* Vs = Qb + NS * M;                       // [var][node]: volume term
-  {
+  if (node) {
     double fb[D][M];
 #pragma unroll
     for (int I = 0; I < D; ++I)
@@ -480,7 +531,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     const double* FbI = Fb + I * M * NS;
     // one (variable, face node) pair per task: traces of q and F_I on both
     // faces normal to I, and the Kv contraction of F_I along the pencil
-    for (int task = a; task < M * NF; task += NS) {
+    for (int task = a; task < M * NF; task += K::TPC) {
       const int v = task / NF, b = task - v * NF;
       double fv[n], vol[n], qL = 0.0, qR = 0.0, fL = 0.0, fR = 0.0;
 #pragma unroll
@@ -520,7 +571,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     }
     __syncthreads();
   });
-  if (live) {
+  if (live && node) {
 #pragma unroll
     for (int v = 0; v < M; ++v) p.Qout[(cell * NS + a) * M + v] = u[v] + cdt * Vs[v * NS + a];
   }
@@ -530,9 +581,11 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     static_for<0, n>([&](auto T_) {
       constexpr int t = decltype(T_)::value;
       __syncthreads();                               // Vs / the last slice read
+      if (node) {
 #pragma unroll
-      for (int v = 0; v < M; ++v) Ts[v * NS + a] = (double)q[t][v];
-      static_for<0, D>([&](auto I_) {
+        for (int v = 0; v < M; ++v) Ts[v * NS + a] = (double)q[t][v];
+      }
+      if (node) static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         if constexpr (K::NQ == 2) {
           Real F[M];
@@ -544,7 +597,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       __syncthreads();
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
-        for (int task = a; task < M * NF; task += NS) {
+        for (int task = a; task < M * NF; task += K::TPC) {
           const int v = task / NF, b = task - v * NF;
           double qL = 0.0, qR = 0.0, fL = 0.0, fR = 0.0;
 #pragma unroll
@@ -580,14 +633,15 @@ template <class K>
 __global__ void __launch_bounds__(K::THREADS) k_pred(const PredP<K> p) {
   constexpr int M = K::M, NS = K::NS;
   __shared__ __align__(16) unsigned char smem[K::LDS_BYTES];
-  const int lc = threadIdx.x / NS;
-  const int a = threadIdx.x - lc * NS;
+  const int lc = threadIdx.x / K::TPC;
+  const int a = threadIdx.x - lc * K::TPC;
   const int64_t cell = (int64_t)blockIdx.x * K::CPB + lc;
   const bool live = cell < p.ncells;
   const int64_t cs = live ? cell : 0;
+  const int an = a < NS ? a : 0;           // threads past the nodes load node 0 (unused)
   double u[M];
 #pragma unroll
-  for (int v = 0; v < M; ++v) u[v] = p.Qin[(cs * NS + a) * M + v];
+  for (int v = 0; v < M; ++v) u[v] = p.Qin[(cs * NS + an) * M + v];
   pred_cell<K>(p, smem + lc * K::CELL_BYTES, a, cell, live, u);
 }
 
@@ -947,8 +1001,8 @@ __global__ void __launch_bounds__(K::THREADS) k_fused(const FusedP<K> f) {
   static_assert(K::CPB * FCB <= 160 * 1024, "fused step LDS exceeds the CU's 160 KiB");
   __shared__ __align__(16) unsigned char smem[K::CPB * FCB];
   __shared__ double red[(K::THREADS + 63) / 64];
-  const int lc = threadIdx.x / NS;
-  const int a = threadIdx.x - lc * NS;
+  const int lc = threadIdx.x / K::TPC;
+  const int a = threadIdx.x - lc * K::TPC;
   const int64_t groups = (f.c.ncells + K::CPB - 1) / K::CPB;
   unsigned char* base = smem + lc * FCB;
   if constexpr (VB == 1) {                  // the sweep: one cell group, maxima and flag
@@ -960,7 +1014,7 @@ __global__ void __launch_bounds__(K::THREADS) k_fused(const FusedP<K> f) {
     double Qn[M];
     double lmax = 0.0;
     int bad = 0;
-    if (act) corr_cell<K, NS>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
+    if (act) corr_cell<K, K::TPC>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
     const double bm = block_max<K::THREADS>(lmax, red);   // ends with a barrier
     if (threadIdx.x == 0) f.c.partial[blockIdx.x] = bm;
     if (bad && f.c.flag) atomicOr(f.c.flag, bad);
@@ -980,7 +1034,7 @@ __global__ void __launch_bounds__(K::THREADS) k_fused(const FusedP<K> f) {
       double lmax = 0.0;
       int bad = 0;
       if (vb > 0) __syncthreads();          // LDS of the previous cell group read
-      if (act) corr_cell<K, NS>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
+      if (act) corr_cell<K, K::TPC>(f.c, reinterpret_cast<double*>(base), a, cell, live, Qn, lmax, bad);
       __syncthreads();                      // corrector LDS read before reuse
       if (act) pred_cell<K>(f.p, base, a, cell, live, Qn);
     }

@@ -6,6 +6,18 @@
 
 namespace adg {
 
+// The bfloat16 predictor (matrix-core contractions) is compiled for the
+// benchmark workloads' orders and the small orders of the tests: 3D Euler
+// N = 3, 4, 7, 3D elasticity N = 5, 3D acoustics N = 3.
+template <template <int> class PDET, int D, int N>
+constexpr bool bf16_instantiated() {
+  if constexpr (D != 3) return false;
+  else if constexpr (std::is_same<PDET<3>, Euler<3>>::value) return N == 3 || N == 4 || N == 7;
+  else if constexpr (std::is_same<PDET<3>, Elastic<3>>::value) return N == 5;
+  else if constexpr (std::is_same<PDET<3>, Acoustic<3>>::value) return N == 3;
+  else return false;
+}
+
 template <template <int> class PDET, int D, int N>
 const Launchers* pick_precision(int prec, bool st) {
   if (st) {     // space-time traces: float64, orders up to 5
@@ -30,6 +42,12 @@ const Launchers* pick_precision(int prec, bool st) {
   if (prec == 1) {
     static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, float>>();
     return &L;
+  }
+  if (prec == 2) {
+    if constexpr (bf16_instantiated<PDET, D, N>()) {
+      static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, float, false, true>>();
+      return &L;
+    }
   }
   return nullptr;
 }

@@ -81,3 +81,46 @@ def test_float_predictor_matches_emulation(pde, dim, order, cells):
           "| per-field rel L2 gpu vs emulation", [f"{x:.2e}" for x in rel_l2(Qg, Qe, s)],
           "| emulation vs float64", [f"{x:.2e}" for x in rel_l2(Qe, Q64, s)])
     assert dev <= 8 * U32 * steps * scale
+
+
+BF16_CASES = [
+    (EULER, 3, 4, (4, 3, 3)),
+    (EULER, 3, 3, (4, 3, 3)),      # two cells per workgroup
+    (EULER, 3, 7, (2, 2, 2)),
+    (ELASTIC, 3, 5, (3, 2, 2)),
+    (ACOUSTIC, 3, 3, (4, 3, 3)),
+]
+
+
+@pytest.mark.parametrize("pde,dim,order,cells", BF16_CASES)
+def test_bf16_predictor_matches_emulation(pde, dim, order, cells):
+    """The bfloat16 predictor (flux differences rounded to bfloat16, D as a
+    bfloat16 pair, float32 accumulation on the matrix cores) against the
+    emulation's "bf16" mode.  Both round x = F - F_ref to bfloat16, but they
+    compute x in float32 in different orders, so an x within float rounding
+    of a bfloat16 rounding boundary may round to the neighbouring bfloat16
+    value on one side only; such a flip moves one contraction input by one
+    bfloat16 unit (2^-8 of it), the size of the bfloat16 effect at that one
+    input.  Bars: per field, the GPU-emulation difference is at most 10% of
+    the emulation's own distance from float64 (rel. L2), and element-wise at
+    most that distance plus the float32 bound of the float predictor."""
+    steps = 2
+    wl, Q0, par, s, Qt, pt, dt = _case(pde, dim, order, cells, inputs.BF16)
+    print("case bf16 emulation", pde, dim, order, cells, "dt", dt, flush=True)
+    Qg, flag, _ = gpu_run(wl, Q0, par, steps, dt=dt)
+    Qe = mixed.run_mixed(Qt, pt, s, steps, "bf16", [dt] * steps)
+    Q64 = Qt
+    for _ in range(steps):
+        Q64 = ostep.step(Q64, pt, dt, s)
+    assert flag == 0
+    e_ge = rel_l2(Qg, Qe, s)
+    e_e64 = rel_l2(Qe, Q64, s)
+    dev = float((Qg - Qe).abs().max())
+    gap = float((Qe - Q64).abs().max())
+    scale = float(Qe.abs().max())
+    print("max |gpu - emulation| / max|Q|", dev / scale, "| max |emulation - float64| / max|Q|",
+          gap / scale,
+          "| per-field rel L2 gpu vs emulation", [f"{x:.2e}" for x in e_ge],
+          "| emulation vs float64", [f"{x:.2e}" for x in e_e64])
+    assert bool((e_ge <= 0.1 * e_e64).all())
+    assert dev <= gap + 8 * U32 * steps * scale
