@@ -345,6 +345,10 @@ def main():
     ap.add_argument("--traces", default="time-integrated", choices=["time-integrated", "spacetime"],
                     help="spacetime: print one line for the headline workload with space-time "
                          "traces and a Rusanov solve per time node")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="predictor precision of the headline line (fp64 is the metric's "
+                         "float64 step; the others are for profiling the reduced-precision "
+                         "kernels alone, with --no-mixed)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -383,7 +387,8 @@ def main():
     fsc = step_flops_per_cell(d, n, m, R, 30)
     hull = 2 * d * 2 * m * n ** (d - 1)                      # hull doubles per cell
     full = args.cells == 81
-    st = Stepper(wl, fused=True)
+    prec = {"fp64": inputs.FP64, "fp32": inputs.FP32, "bf16": inputs.BF16}[args.precision]
+    st = Stepper(wl.with_(precision=prec), fused=True)
     print("[bench] fp64 fused run", file=sys.stderr, flush=True)
     Q64, wall, sweep, reruns, dts = run_fused_path(st, Q0, args.steps, args.warmup, wl.cfl,
                                                    C_DT, torch)
@@ -397,7 +402,8 @@ def main():
         "metric": METRIC, "value": dofs * args.steps / wall, "unit": "DoF-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"3D compressible Euler N=4, {args.cells}^3 periodic cells "
                                "on [0,1]^3, Gaussian density bump, Rusanov, adaptive dt: "
@@ -405,7 +411,7 @@ def main():
                                "average and device-side reruns (shifted, fused, optimistic "
                                "stepping, Alg. 2; 0.5625 = 0.9 of the N=4 stability limit)",
                    "cells": wl.ncells, "dofs_per_cell": wl.dofs_per_cell,
-                   "picard_iters": R, "precision": "fp64", "stepping": "fused (Alg. 2)"},
+                   "picard_iters": R, "precision": args.precision, "stepping": "fused (Alg. 2)"},
         "kernel_ms": {"sweep": sweep},
         "reruns": reruns,
         "dt_first_last": [float(dts[0]), float(dts[args.steps - 1])],
@@ -418,7 +424,7 @@ def main():
                      "hbm_frac": wl.ncells * (2 * wl.dofs_per_cell * 8 + 2 * hull * 8)
                                  / (sweep * 1e-3) / (HBM_PEAK_GBPS * 1e9),
                      "binding": "alu (FP64 VALU and LDS; hbm_frac is far lower)",
-                     "traffic": measured_traffic("k_fused_fp64") if full else None,
+                     "traffic": measured_traffic("k_fused_fp64") if full and prec == 0 else None,
                      "traffic_unit": "bytes per launch",
                      "algorithmic_bytes": wl.ncells * (2 * wl.dofs_per_cell * 8 + 2 * hull * 8),
                      "flops_per_cell": fsc,
@@ -435,13 +441,13 @@ def main():
             "predict_roofline": {"kernel": "k_pred (adg_predict)", "bound": "alu",
                                  "achieved": pred_achieved, "peak": FP64_PEAK_TFLOPS,
                                  "unit": "TFLOP/s", "frac": pred_achieved / FP64_PEAK_TFLOPS,
-                                 "traffic": measured_traffic("k_pred_fp64") if full else None,
+                                 "traffic": measured_traffic("k_pred_fp64") if full and prec == 0 else None,
                                  "algorithmic_bytes": wl.ncells * (wl.dofs_per_cell * 8 * 2
                                                                    + hull * 8)},
             "correct_hbm": {"achieved_GBps": corr_bytes_per_cell(d, n, m, 8) * wl.ncells
                             / (corr * 1e-3) / 1e9, "peak_GBps": 8000.0,
                             "algorithmic_bytes": corr_bytes_per_cell(d, n, m, 8) * wl.ncells,
-                            "traffic": measured_traffic("k_corr_fp64") if full else None}},
+                            "traffic": measured_traffic("k_corr_fp64") if full and prec == 0 else None}},
     }
     if not args.no_mixed:
         out.update(mixed_paths(args, wl, Q0, dofs, torch))

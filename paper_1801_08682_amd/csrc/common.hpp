@@ -63,6 +63,7 @@ struct KTab {
   // Dl = bf16(fl32(D - Dh)), both round to nearest even (bit patterns); their
   // sum is a 16-bit-significand operator that float32 holds exactly.
   uint16_t Dh[n][n], Dl[n][n];
+  float Dx[n][n];   // Dh + Dl as a float (exact)
 };
 
 // float -> bfloat16 bit pattern, round to nearest, ties to even (finite x).
@@ -110,6 +111,7 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
       const double d = h.D[k * n + j];
       t.Dh[k][j] = bf16_bits_rne((float)d);
       t.Dl[k][j] = bf16_bits_rne((float)(d - bf16_bits_value(t.Dh[k][j])));
+      t.Dx[k][j] = (float)(bf16_bits_value(t.Dh[k][j]) + bf16_bits_value(t.Dl[k][j]));
     }
   return t;
 }
@@ -118,18 +120,22 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
 // Operand layout of that instruction (verified on the device): lane l holds
 // A[l % 16][8 (l / 16) + r] and B[8 (l / 16) + r][l % 16] in its register r
 // (r < 8) and receives C[4 (l / 16) + i][l % 16] (i < 4).  With A block
-// diagonal, A[4 g + i][8 g + j] = Dsel[4 h + i][j] for lane group g = l / 16,
-// each lane's 8 B values (its own pencil's inputs x_j, j < n) produce
-// sum_j Dsel[4 h + i][j] x_j, i < 4, in its own C: a per-lane contraction of
-// four output nodes (h = 0: nodes 0..3, h = 1: nodes 4..7).  Every lane of
-// the wave takes part; lanes without a task must hold finite inputs.
+// diagonal, A[4 g + i][8 g + j] = R_i[j] for lane group g = l / 16, each
+// lane's 8 B values (its own pencil's inputs x_j, j < n) produce
+// sum_j R_i[j] x_j, i < 4, in its own C: a per-lane contraction against four
+// operator rows R_0..R_3.  Nodes 0..3 take two instructions (rows of Dh, then
+// rows of Dl accumulated); nodes 4..n-1 one more when n <= 6 (rows
+// Dh[4..n-1] and Dl[4..n-1] side by side, summed afterwards) and two when
+// n > 6.  Every lane of the wave takes part; lanes without a task must hold
+// finite inputs.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <int n>
 struct MxOps {
   static constexpr int NH = n > 4 ? 2 : 1;          // output halves
-  bf16x8 hi[NH], lo[NH];
+  static constexpr bool PACK1 = n > 4 && n <= 6;    // second half: Dh and Dl rows in one operand
+  bf16x8 hi[NH], lo[NH];                            // lo[1] unused when PACK1
 };
 
 template <int n, class Tab>
@@ -149,6 +155,19 @@ __device__ __forceinline__ MxOps<n> make_mx_ops(const Tab& t) {
       const uint16_t bl = on ? t.Dl[row < n ? row : 0][r < n ? r : 0] : (uint16_t)0;
       o.hi[h][r] = __builtin_bit_cast(__bf16, bh);
       o.lo[h][r] = __builtin_bit_cast(__bf16, bl);
+    }
+  }
+  if constexpr (MxOps<n>::PACK1) {
+    // rows i < n - 4: Dh[4 + i]; rows n - 4 <= i < 2 (n - 4): Dl[4 + i - (n - 4)]
+    const int i = m & 3;
+    const bool hi_row = i < n - 4, lo_row = i >= n - 4 && i < 2 * (n - 4);
+    const int row = 4 + (hi_row ? i : (lo_row ? i - (n - 4) : 0));
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const bool on = mine && r < n && (hi_row || lo_row);
+      const int rr = r < n ? r : 0;
+      const uint16_t b = on ? (hi_row ? t.Dh[row][rr] : t.Dl[row][rr]) : (uint16_t)0;
+      o.hi[1][r] = __builtin_bit_cast(__bf16, b);
     }
   }
   return o;
@@ -172,20 +191,32 @@ __device__ __forceinline__ void pencil_dF_mx(const MxOps<n>& A, FluxAt&& flux_at
   float F[n][M];
 #pragma unroll
   for (int j = 0; j < n; ++j) flux_at(j, F[j]);
+  constexpr int jr = (n < 5) ? 0 : ((n % 2 == 1) ? n / 2 : -1);   // x_jr = 0 exactly
 #pragma unroll
   for (int v = 0; v < M; ++v) {
     const float Fr = pencil_ref<n, M>(F, v);
     bf16x8 B;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) B[r] = r < n ? (__bf16)(F[r < n ? r : 0][v] - Fr) : (__bf16)0.0f;
+    for (int r = 0; r < 8; ++r)
+      B[r] = (r < n && r != jr) ? (__bf16)(F[r < n ? r : 0][v] - Fr) : (__bf16)0.0f;
+    floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[0], B, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[0], B, c, 0, 0, 0);
 #pragma unroll
-    for (int h = 0; h < MxOps<n>::NH; ++h) {
-      floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[h], B, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[h], B, c, 0, 0, 0);
+    for (int i = 0; i < 4; ++i)
+      if (i < n) out[i][v] = c[i];
+    if constexpr (MxOps<n>::PACK1) {
+      floatx4 e = {0.0f, 0.0f, 0.0f, 0.0f};
+      e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[1], B, e, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < n - 4; ++i) out[4 + i][v] = e[i] + e[i + (n - 4)];
+    } else if constexpr (MxOps<n>::NH == 2) {
+      floatx4 e = {0.0f, 0.0f, 0.0f, 0.0f};
+      e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[1], B, e, 0, 0, 0);
+      e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[1], B, e, 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if (4 * h + i < n) out[4 * h + i][v] = c[i];
+        if (4 + i < n) out[4 + i][v] = e[i];
     }
   }
 }

@@ -362,10 +362,8 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
           const float Fr = pencil_ref<n, M>(F, v);
 #pragma unroll
           for (int j = 0; j < n; ++j) {
-            const float dh = __builtin_bit_cast(float, (uint32_t)p.t.Dh[ai][j] << 16);
-            const float dl = __builtin_bit_cast(float, (uint32_t)p.t.Dl[ai][j] << 16);
             const float x = (float)(__bf16)(F[j][v] - Fr);
-            rv[v] = fma(dh + dl, x, rv[v]);
+            rv[v] = fma(p.t.Dx[ai][j], x, rv[v]);
           }
         }
       } else {
