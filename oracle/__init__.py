@@ -34,9 +34,11 @@ fused        shifted, fused, optimistic time stepping (Alg. 2)
 spacetime    the step with space-time traces and per-time-node Rusanov (Table 1)
 mixed        the step with a float32 or bfloat16-input predictor and a float64
              corrector (precision emulation of the mixed GPU path)
+fv           finite-volume subcell patches of the limiter: projection, least-
+             squares reconstruction and the first-order Rusanov step (App. A)
 
 Every function works on float64 torch CPU tensors so that torch.autograd gives
 an adjoint that shares nothing with the hand-written GPU adjoint.
 """
 
-from . import tables, pde, step, diagnostics, fused, spacetime, mixed  # noqa: F401
+from . import tables, pde, step, diagnostics, fused, spacetime, mixed, fv  # noqa: F401
