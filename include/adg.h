@@ -183,6 +183,34 @@ adg_status adg_fused_begin(adg_ctx* ctx, double* d_Q, const double* d_params, do
 adg_status adg_fused_sweep(adg_ctx* ctx);
 adg_status adg_fused_end(adg_ctx* ctx);
 
+/* Finite-volume subcell patches of the limiter (Sec. 3, "Finite Volume
+ * limiter"; App. A, Corollary 8).  Every cell carries S^d subcells,
+ * S = 2N + 1, as P[cell][subcell][var] (float64; subcells lexicographic with
+ * the x index fastest, var innermost: S^d m values per cell).  Each call
+ * reads d_in/d_P and writes the other buffer (distinct, caller-owned,
+ * 16-byte aligned); contexts with precision ADG_FP64 and time-integrated
+ * traces only (else ADG_ERR_UNSUPPORTED).
+ *
+ * adg_fv_project: P = the exact average of each cell's polynomial Q over
+ * each subcell (tensor product of the per-axis averages of the Lagrange
+ * basis).
+ * adg_fv_reconstruct: Q = the least-squares DG solution whose subcell
+ * averages best match P (per axis (Pi^T Pi)^-1 Pi^T); it inverts
+ * adg_fv_project on DG data.
+ * adg_fv_step: one first-order finite-volume step with Rusanov fluxes on the
+ * periodic subgrid of spacing h / S, i.e. ADER-DG with p = 0 there (the
+ * predictor is the identity, the face traces are the subcells' own states
+ * and fluxes, Corollary 8): d_Pout = d_P - (dt S / h) sum_i (F*_{i,+} -
+ * F*_{i,-}), F* = (f_L + f_R)/2 - s (P_R - P_L)/2 with s = max(lambda_L,
+ * lambda_R) per face; a subcell takes its cell's material.  Records the
+ * per-block maxima of the new state's wave speeds, so adg_cfl_dt then gives
+ * cfl (h/S) / (d lambda_max), the subgrid's admissible step (h/S is exactly
+ * the h / (2N + 1) of the DG step's formula).  d_flag as in adg_correct. */
+adg_status adg_fv_project(adg_ctx* ctx, const double* d_Q, double* d_P);
+adg_status adg_fv_reconstruct(adg_ctx* ctx, const double* d_P, double* d_Q);
+adg_status adg_fv_step(adg_ctx* ctx, const double* d_P, double* d_Pout, const double* d_params,
+                       const double* d_dt, int32_t* d_flag);
+
 /* Reverse mode of one adg_step with dt held fixed (the discrete adjoint of
  * Eq. (5)/(6) including the Picard iterations and the Rusanov maximum; the
  * maximum passes its derivative to the first maximal face node, left state

@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "ADG_OK", 1: "ADG_ERR_INVALID_ARG", 2: "ADG_ERR_UNSUPPORTED",
 
 EXPORTS = ["adg_query", "adg_init", "adg_predict", "adg_correct", "adg_step",
            "adg_wave_speed", "adg_cfl_dt", "adg_step_adjoint", "adg_run_fused", "adg_fused_begin",
-           "adg_fused_sweep", "adg_fused_end", "adg_step_noalloc", "adg_destroy",
+           "adg_fused_sweep", "adg_fused_end", "adg_step_noalloc", "adg_fv_project",
+           "adg_fv_reconstruct", "adg_fv_step", "adg_destroy",
            "adg_last_error", "adg_version"]
 
 
@@ -72,6 +73,9 @@ def load(path=LIB_PATH):
         "adg_fused_sweep": [vp],
         "adg_fused_end": [vp],
         "adg_step_noalloc": [vp, dp, dp, dp, ip, dp],
+        "adg_fv_project": [vp, dp, dp],
+        "adg_fv_reconstruct": [vp, dp, dp],
+        "adg_fv_step": [vp, dp, dp, dp, dp, ip],
         "adg_destroy": [vp],
     }
     for name, args in sig.items():

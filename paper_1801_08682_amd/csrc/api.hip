@@ -617,6 +617,56 @@ adg_status adg_run_fused(adg_ctx* ctx, double* d_Q, const double* d_params, int3
   return adg_fused_end(ctx);
 }
 
+static adg_status fv_check(adg_ctx* ctx, const void* in, const void* out) {
+  if (!ctx) { g_err = "ctx is NULL"; return ADG_ERR_INVALID_ARG; }
+  if (ctx->static_ws)
+    return ctx->fail(ADG_ERR_WORKSPACE, "context has no workspace: only adg_step_noalloc runs on it");
+  if (!in || !out) return ctx->fail(ADG_ERR_INVALID_ARG, "input and output buffers are required");
+  if (!aligned16(in) || !aligned16(out))
+    return ctx->fail(ADG_ERR_INVALID_ARG, "device buffers must be 16-byte aligned");
+  if (in == out) return ctx->fail(ADG_ERR_INVALID_ARG, "input and output must be distinct buffers");
+  if (!ctx->L->fv_step)
+    return ctx->fail(ADG_ERR_UNSUPPORTED, "subcell patches need precision ADG_FP64 and "
+                                          "time-integrated traces");
+  return ADG_OK;
+}
+
+adg_status adg_fv_project(adg_ctx* ctx, const double* d_Q, double* d_P) {
+  adg_status s = fv_check(ctx, d_Q, d_P);
+  if (s != ADG_OK) return s;
+  adg::LaunchArgs a = ctx->args();
+  a.qin = d_Q;
+  a.qout = d_P;
+  return ctx->launched(ctx->L->fv_project(a), "fv_project");
+}
+
+adg_status adg_fv_reconstruct(adg_ctx* ctx, const double* d_P, double* d_Q) {
+  adg_status s = fv_check(ctx, d_P, d_Q);
+  if (s != ADG_OK) return s;
+  adg::LaunchArgs a = ctx->args();
+  a.qin = d_P;
+  a.qout = d_Q;
+  return ctx->launched(ctx->L->fv_reconstruct(a), "fv_reconstruct");
+}
+
+adg_status adg_fv_step(adg_ctx* ctx, const double* d_P, double* d_Pout, const double* d_params,
+                       const double* d_dt, int32_t* d_flag) {
+  adg_status s = fv_check(ctx, d_P, d_Pout);
+  if (s != ADG_OK) return s;
+  if (!d_dt) return ctx->fail(ADG_ERR_INVALID_ARG, "dt is required");
+  if (n_params(ctx->cfg.pde) > 0 && !d_params)
+    return ctx->fail(ADG_ERR_INVALID_ARG, "this PDE needs per-cell params");
+  if (d_params && !aligned16(d_params))
+    return ctx->fail(ADG_ERR_INVALID_ARG, "device buffers must be 16-byte aligned");
+  adg::LaunchArgs a = ctx->args();
+  a.qin = d_P;
+  a.qout = d_Pout;
+  a.params = d_params;
+  a.dt = d_dt;
+  a.flag = d_flag;
+  return ctx->launched(ctx->L->fv_step(a), "fv_step");
+}
+
 adg_status adg_step_adjoint(adg_ctx* ctx, const double* d_Qn, const double* d_params, const double* d_dt,
                             double* d_Qbar, double* d_params_bar) {
   adg_status s = check_state(ctx, d_Qn, d_params, d_dt);

@@ -383,6 +383,9 @@ struct Launchers {
   LaunchFn wave_speed = nullptr;
   LaunchFn adjoint = nullptr;
   LaunchFn fused = nullptr;
+  LaunchFn fv_project = nullptr;       // subcell patches of the limiter (float64)
+  LaunchFn fv_reconstruct = nullptr;
+  LaunchFn fv_step = nullptr;
   int64_t trace_bytes_per_cell = 0;
   int64_t qdofs_per_cell = 0;                  // m (N+1)^d
   int64_t (*adj_slot_doubles)(int R) = nullptr;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "kernels_adj.hpp"
+#include "kernels_fv.hpp"
 
 namespace adg {
 
@@ -34,6 +35,9 @@ const Launchers* pick_precision(int prec, bool st) {
     static const Launchers L = [] {
       Launchers l = make_fwd_launchers<K>();
       l.adjoint = &launch_adjoint<K>;
+      l.fv_project = &launch_fv_project<K>;
+      l.fv_reconstruct = &launch_fv_reconstruct<K>;
+      l.fv_step = &launch_fv_step<K>;
       l.adj_slot_doubles = [](int R) { return adj_slot_doubles<K>(R); };
       return l;
     }();

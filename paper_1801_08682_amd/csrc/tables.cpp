@@ -136,6 +136,28 @@ bool build_tables(int n, HostTables* t) {
     t->LL[k] = t->FL[k] / t->w[k];
     t->LR[k] = t->FR[k] / t->w[k];
   }
+  // subcell averages: Pi[s][j] = sum_q w_q phi_j((s + xi_q) / S)
+  const int S = 2 * n - 1;
+  t->S = S;
+  t->Pi.assign(S * n, 0.0);
+  std::vector<double> phi(n);
+  for (int sc = 0; sc < S; ++sc)
+    for (int q = 0; q < n; ++q) {
+      lagrange_at(t->xi, lam, (sc + t->xi[q]) / S, phi.data());
+      for (int j = 0; j < n; ++j) t->Pi[sc * n + j] += t->w[q] * phi[j];
+    }
+  // least-squares reconstruction Rc = (Pi^T Pi)^-1 Pi^T
+  std::vector<double> A(n * n, 0.0), I(n * n, 0.0), Ainv;
+  for (int a = 0; a < n; ++a) {
+    I[a * n + a] = 1.0;
+    for (int b = 0; b < n; ++b)
+      for (int sc = 0; sc < S; ++sc) A[a * n + b] += t->Pi[sc * n + a] * t->Pi[sc * n + b];
+  }
+  if (!solve(n, A, I, &Ainv)) return false;
+  t->Rc.assign(n * S, 0.0);
+  for (int a = 0; a < n; ++a)
+    for (int sc = 0; sc < S; ++sc)
+      for (int b = 0; b < n; ++b) t->Rc[a * S + sc] += Ainv[a * n + b] * t->Pi[sc * n + b];
   return true;
 }
 

@@ -9,6 +9,11 @@
 //   P        = K1^-1 diag(w)                     Picard time operator
 //   Kv[a][j] = w_j D[j][a] / w_a                 volume term of the update
 //   LL, LR   = FL / w, FR / w                    face lifting
+// and, for the limiter's subcell patches (S = 2N + 1 = 2n - 1 subcells per
+// axis; Sec. 3 "Finite Volume limiter"):
+//   Pi[s][j] = average of phi_j over subcell s     (S x n, an n-point Gauss
+//                                                 rule per subcell: exact)
+//   Rc = (Pi^T Pi)^-1 Pi^T                        (n x S, least squares back)
 // Computed on the host in double precision; no device code here.
 #pragma once
 
@@ -19,6 +24,8 @@ namespace adg {
 struct HostTables {
   int n = 0;
   std::vector<double> xi, w, D, FL, FR, P, Kv, LL, LR;   // row-major n x n where 2D
+  int S = 0;
+  std::vector<double> Pi, Rc;                            // S x n and n x S, row-major
 };
 
 // Returns false when n is outside [1, 16].

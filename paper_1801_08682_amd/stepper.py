@@ -114,6 +114,29 @@ class Stepper:
     def fused_end(self):
         self._check(self.L.adg_fused_end(self.ctx))
 
+    # -- finite-volume subcell patches (S = 2N + 1 subcells per axis) --
+    @property
+    def subcells(self):
+        return 2 * self.wl.order + 1
+
+    def _patch(self, P):
+        wl = self.wl
+        want = (wl.ncells, self.subcells ** wl.dim, wl.m)
+        if P.dtype != torch.float64 or not P.is_contiguous() or tuple(P.shape) != want \
+                or P.device.type != "cuda":
+            raise ValueError(f"patches must be a contiguous float64 device tensor of shape {want}")
+        return _ptr(P)
+
+    def fv_project(self, Q, P):
+        self._check(self.L.adg_fv_project(self.ctx, self._q(Q), self._patch(P)))
+
+    def fv_reconstruct(self, P, Q):
+        self._check(self.L.adg_fv_reconstruct(self.ctx, self._patch(P), self._q(Q)))
+
+    def fv_step(self, P, Pout, params, dt, flag=None):
+        self._check(self.L.adg_fv_step(self.ctx, self._patch(P), self._patch(Pout),
+                                       self._p(params), _ptr(dt), _ptr(flag)))
+
     def close(self):
         if self.ctx:
             self.L.adg_destroy(self.ctx)
