@@ -153,3 +153,131 @@ def test_rollout_final_kinetic_energy_euler():
     print("dKE/drho0 rel err", err)
     assert err < 1e-9
     st.close()
+
+
+def test_rollout_final_kinetic_energy_euler_n7_fd():
+    """C5 at its order: Euler N=7 (8^3 nodes per cell) on 2 x 2 x 1 cells, Fourier
+    density with p = rho^gamma, 12 steps with the device-computed dt,
+    checkpoint every 10 (two segments).  The gradient of the final kinetic
+    energy w.r.t. the initial density DoFs is taken with the recorded dt
+    sequence held fixed (the dependence of dt on the state through the wave
+    speed maximum is not differentiated); against the oracle's autograd with
+    the same dts, and against central differences of the GPU forward run
+    with the same dts on 4 seeded directions and 8 sampled coordinates."""
+    wl = inputs.preset("C5").with_(n_cells=(2, 2, 1), length=2 / 48)
+    Q0 = inputs.initial_state(wl, seed=0)
+    steps, k = 12, 10
+    st = Stepper(wl, adjoint=True)
+    z, om = np.polynomial.legendre.leggauss(wl.n)
+    w1 = torch.tensor(0.5 * om, device="cuda")
+    print("case C5 N=7 KE gradient", flush=True)
+    Qg = torch.tensor(Q0, device="cuda", requires_grad=True)
+    QN, _ = rollout(st, Qg, None, steps, cfl=wl.cfl, checkpoint_every=k)
+    KE = kinetic_energy(QN, 3, wl.h, w1)
+    KE.backward()
+    g = Qg.grad[..., 0].detach()
+    Q = torch.tensor(Q0, device="cuda")
+    dts = [float(x.item()) for x in st.run(Q, None, steps, cfl=wl.cfl, record_dt=True)]
+    Jo, go = oadj.grad_final_ke(torch.tensor(Q0), setup_of(wl), dts)
+    print("KE gpu", float(KE), "oracle", Jo)
+    assert abs(float(KE) - Jo) <= 1e-10 * abs(Jo)
+    err = float((g.cpu() - go[..., 0]).norm() / go[..., 0].norm())
+    print("dKE/drho0 rel err vs oracle", err)
+    assert err < 1e-9
+
+    dtd = [st.scalar(x) for x in dts]
+
+    def J(X):
+        Y = X.clone()
+        for x in dtd:
+            st.step(Y, None, x)
+        return float(kinetic_energy(Y, 3, wl.h, w1))
+    rng = np.random.default_rng(3)
+    Q0d = torch.tensor(Q0, device="cuda")
+    rho = Q0d[..., 0]
+    gmax = float(g.abs().max())
+    for kdir in range(4):
+        v = torch.zeros_like(Q0d)
+        v[..., 0] = torch.tensor(rng.standard_normal(tuple(rho.shape)), device="cuda")
+        eps = 1e-6 * float(rho.norm()) / float(v.norm())
+        fd = (J(Q0d + eps * v) - J(Q0d - eps * v)) / (2 * eps)
+        an = float((g * v[..., 0]).sum())
+        print("direction", kdir, "fd", fd, "adjoint", an)
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    flat = rng.choice(rho.numel(), 8, replace=False)
+    for f in flat:
+        c_, a_ = divmod(int(f), rho.shape[1])
+        v = torch.zeros_like(Q0d)
+        v[c_, a_, 0] = 1.0
+        eps = 1e-6 * float(rho.norm())
+        fd = (J(Q0d + eps * v) - J(Q0d - eps * v)) / (2 * eps)
+        an = float(g[c_, a_])
+        print("coordinate", (c_, a_), "fd", fd, "adjoint", an)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * gmax)
+    st.close()
+
+
+def test_rollout_receiver_misfit_fd_directions_and_coordinates():
+    """C4 reduced (acoustics N=3, 5^3 cells, per-cell sound speed, 12 steps,
+    checkpoint every 5, 8 receivers): the misfit gradient against central
+    differences on 8 seeded directions in (initial pressure DoFs, sound
+    speed) jointly and on 16 sampled coordinates (8 pressure DoFs, 8 cells'
+    sound speeds), eps = 1e-6 |theta| / |v|; relative bar 1e-6 (coordinates
+    whose gradient is below 1e-3 of the largest are held to 1e-6 of that)."""
+    wl = inputs.preset("C4").with_(n_cells=(5, 5, 5))
+    Q0 = torch.tensor(inputs.initial_state(wl), device="cuda")
+    c = torch.tensor(inputs.cell_params(wl, seed=0), device="cuda")
+    ctrue = torch.tensor(inputs.cell_params(wl, seed=2), device="cuda")
+    pts = inputs.receivers(8, 3, seed=1)
+    dt = wl.cfl * wl.h / (3 * 7 * float(c.max()))
+    steps, k = 12, 5
+    st = Stepper(wl, adjoint=True)
+    rc, rr = receiver_rows(wl, pts)
+    rec = (torch.tensor(rc, device="cuda"), torch.tensor(rr, device="cuda"))
+    print("case C4 FD directions", flush=True)
+    with torch.no_grad():
+        _, data = rollout(st, Q0, ctrue, steps, dt=dt, checkpoint_every=k, receivers=rec)
+    Qg, cg = Q0.clone().requires_grad_(True), c.clone().requires_grad_(True)
+    _, smp = rollout(st, Qg, cg, steps, dt=dt, checkpoint_every=k, receivers=rec)
+    (0.5 * ((smp - data) ** 2).sum()).backward()
+    gp, gc = Qg.grad[..., 0].detach(), cg.grad.detach()
+
+    def J(Qx, cx):
+        with torch.no_grad():
+            _, sm = rollout(st, Qx, cx, steps, dt=dt, checkpoint_every=k, receivers=rec)
+        return float(0.5 * ((sm - data) ** 2).sum())
+    p0 = Q0[..., 0]
+    theta = float(torch.sqrt((p0 ** 2).sum() + (c ** 2).sum()))
+    rng = np.random.default_rng(3)
+    for kdir in range(8):
+        vp = torch.tensor(rng.standard_normal(tuple(p0.shape)), device="cuda")
+        vc = torch.tensor(rng.standard_normal(tuple(c.shape)), device="cuda")
+        eps = 1e-6 * theta / float(torch.sqrt((vp ** 2).sum() + (vc ** 2).sum()))
+        Qp, Qm = Q0.clone(), Q0.clone()
+        Qp[..., 0] += eps * vp
+        Qm[..., 0] -= eps * vp
+        fd = (J(Qp, c + eps * vc) - J(Qm, c - eps * vc)) / (2 * eps)
+        an = float((gp * vp).sum() + (gc * vc).sum())
+        print("direction", kdir, "fd", fd, "adjoint", an)
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    gpm, gcm = float(gp.abs().max()), float(gc.abs().max())
+    for f in rng.choice(p0.numel(), 8, replace=False):
+        c_, a_ = divmod(int(f), p0.shape[1])
+        eps = 1e-6 * theta
+        Qp, Qm = Q0.clone(), Q0.clone()
+        Qp[c_, a_, 0] += eps
+        Qm[c_, a_, 0] -= eps
+        fd = (J(Qp, c) - J(Qm, c)) / (2 * eps)
+        an = float(gp[c_, a_])
+        print("pressure DoF", (c_, a_), "fd", fd, "adjoint", an)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * gpm)
+    for f in rng.choice(c.shape[0], 8, replace=False):
+        eps = 1e-6 * theta
+        cp_, cm_ = c.clone(), c.clone()
+        cp_[int(f), 0] += eps
+        cm_[int(f), 0] -= eps
+        fd = (J(Q0, cp_) - J(Q0, cm_)) / (2 * eps)
+        an = float(gc[int(f), 0])
+        print("sound speed", int(f), "fd", fd, "adjoint", an)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * gcm)
+    st.close()
