@@ -120,7 +120,13 @@ struct Fwd {
   static constexpr int PIC_BYTES = (ALIAS ? 1 : 2) * S * NSP * MP * (int)sizeof(Real);
   static constexpr int FIRST_BYTES = D * NSP * MP * (int)sizeof(Real);   // d flux planes of u
   static constexpr int max3(int x, int y, int z) { return x > y ? (x > z ? x : z) : (y > z ? y : z); }
-  static constexpr int CELL_BYTES = (max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES) + 15) / 16 * 16;
+  // Linear flux: the predictor as powers of the spatial operator (no time
+  // slices in LDS; see pred_cell).  Not for the matrix-core form, whose
+  // rounding of the Picard contractions' inputs is part of its definition.
+  static constexpr bool CK = PDE::LINEAR && !ST_ && !MX_;
+  static constexpr int CELL_BYTES =
+      ((CK ? (FIRST_BYTES > FIN_BYTES ? FIRST_BYTES : FIN_BYTES)
+           : max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES)) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
   // per cell; layout [face][time][qty][var][face node] (face nodes fastest:
@@ -204,6 +210,7 @@ struct PredP {
   double inv_h;
   int R;
   Gconst<typename K::Real> g;
+  Gconst<double> gd;     // the same constants in float64 (float64 finalisation)
   KTab<K::n, typename K::Real> t;
 };
 
@@ -320,15 +327,17 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   // from the d pencils through it (all lanes busy, one barrier).  In float
   // the gather subtracts the node's own flux first (zero row sums of D), so
   // that a constant state has exactly zero derivative.
-  auto first_iteration = [&]() {
+  // rv = sum_i D_i F_i(x) at this node for a field x given per node (every
+  // node thread its own value): the node threads write their d fluxes of x,
+  // then gather from the d pencils through their node (one barrier before,
+  // one after, which frees Fs).
+  auto gather_L = [&](const Real (&x)[M], Real (&rv)[M]) {
     Real* Fs = reinterpret_cast<Real*>(base);      // [axis][var][node] planes
     constexpr bool REF = !std::is_same<Real, double>::value;
     Real Fo[REF ? D : 1][M];
     if (node) {
-      Real uu[M], w[M];
-#pragma unroll
-      for (int v = 0; v < M; ++v) uu[v] = (Real)u[v];
-      PDE::pub(uu, w, p.g);
+      Real w[M];
+      PDE::pub(x, w, p.g);
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         Real F[M];
@@ -341,7 +350,6 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       });
     }
     __syncthreads();
-    Real rv[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) rv[v] = Real(0);
     if (node) static_for<0, D>([&](auto I_) {
@@ -381,15 +389,64 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         }
       }
     });
+    __syncthreads();                                // Fs is reused after
+  };
+  auto first_iteration = [&]() {
+    Real uu[M], rv[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) uu[v] = (Real)u[v];
+    gather_L(uu, rv);
 #pragma unroll
     for (int v = 0; v < M; ++v)
 #pragma unroll
       for (int t = 0; t < n; ++t) q[t][v] = (Real)u[v] - c * (p.t.Ps[t] * rv[v]);
-    __syncthreads();                                // Fs is reused below
   };
 
   // ---- predict: Picard iteration q <- u - (dt/h) P sum_i D_i F_i(q) ----
-  if constexpr (K::ALIAS) {
+  [[maybe_unused]] double qbar_ck[M];
+  if constexpr (K::CK) {
+    // Linear flux: rhs(q) = L q slice by slice, L = sum_i D_i F_i, so from
+    // q^0 = 1 (x) u the iterates are q^r = sum_{k<=r} (-c)^k T_k (x) L^k u
+    // with T_0 = 1, T_k = P^{k-1} Ps (the time operator commutes with L),
+    // exactly, R applications of L to one spatial field instead of R sweeps
+    // over the n time slices.  The finalisation needs only the time average
+    // qbar = sum_k (-c)^k (w . T_k) L^k u (linear fluxes: Fbar = F(qbar)).
+    Real vk[M];
+    double T[n];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      vk[v] = (Real)u[v];
+      qbar_ck[v] = u[v];
+    }
+#pragma unroll
+    for (int t = 0; t < n; ++t) T[t] = (double)p.t.Ps[t];
+    double ck = 1.0;
+    for (int k = 1; k <= p.R; ++k) {
+      if (k > 1) {
+        double Tn[n];
+#pragma unroll
+        for (int t = 0; t < n; ++t) {
+          double a2 = 0.0;
+#pragma unroll
+          for (int tt = 0; tt < n; ++tt) a2 = fma((double)p.t.P[t][tt], T[tt], a2);
+          Tn[t] = a2;
+        }
+#pragma unroll
+        for (int t = 0; t < n; ++t) T[t] = Tn[t];
+      }
+      Real rv[M];
+      gather_L(vk, rv);
+      ck *= -cdt;
+      double beta = 0.0;
+#pragma unroll
+      for (int t = 0; t < n; ++t) beta = fma(p.t.w[t], T[t], beta);
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        vk[v] = rv[v];
+        qbar_ck[v] = fma(ck * beta, (double)rv[v], qbar_ck[v]);
+      }
+    }
+  } else if constexpr (K::ALIAS) {
     // One pencil per axis per thread and slice: evaluate F_I along the
     // pencil, contract with D, keep the result in registers.
     auto pencils = [&](auto NS_, auto& out) {
@@ -493,7 +550,20 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   double* Fb = reinterpret_cast<double*>(base);   // [axis][var][node]: time-averaged F_i
   double* Qb = Fb + D * NS * M;                   // [var][node]: time-averaged q
   double* Vs = Qb + NS * M;                       // [var][node]: volume term
-  if (node) {
+  if (node && K::CK) {
+    if constexpr (K::CK) {
+      const auto cpd = PDE::template cell<double>(p.par + cs * K::NPAR);
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qb[v * NS + a] = qbar_ck[v];
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        double F[M];
+        PDE::template flux<I>(qbar_ck, F, p.gd, cpd);
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fb[(I * M + v) * NS + a] = F[v];
+      });
+    }
+  } else if (node) {
     double fb[D][M];
 #pragma unroll
     for (int I = 0; I < D; ++I)
@@ -1083,7 +1153,10 @@ PredP<K> pred_params(const LaunchArgs& a) {
   p.ncells = a.ncells;
   p.inv_h = a.inv_h;
   p.R = a.R;
-  for (int k = 0; k < 4; ++k) p.g.c[k] = (Real)a.gp[k];
+  for (int k = 0; k < 4; ++k) {
+    p.g.c[k] = (Real)a.gp[k];
+    p.gd.c[k] = a.gp[k];
+  }
   p.t = make_ktab<K::n, Real>(*a.tab);
   return p;
 }
