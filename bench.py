@@ -166,10 +166,27 @@ def adjoint_bench(args):
     J.backward()
     torch.cuda.synchronize()
     t_fb = time.perf_counter() - t0
+    # one adg_step_adjoint against one adg_step, both alone on the device
+    Qs, Gs, pb = Q0.clone(), torch.randn_like(Q0), torch.zeros_like(c)
+    dts = st.scalar(dt)
+    reps = 20
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    st.step_adjoint(Qs, c, dts, Gs, pb)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        st.step(Qs, c, dts)
+    ev[1].record()
+    for _ in range(reps):
+        st.step_adjoint(Qs, c, dts, Gs, pb)
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd_ms, adj_ms = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
     st.close()
     return {"workload": f"3D acoustics N=3, 48^3 cells, {steps} steps, 64 receivers, "
                         f"checkpoint every {k}", "forward_s": t_fwd,
-            "forward_plus_backward_s": t_fb, "ratio": t_fb / t_fwd, "J": float(J),
+            "forward_plus_backward_s": t_fb, "ratio": t_fb / t_fwd, "J": float(J.detach()),
+            "step_ms": fwd_ms, "adjoint_step_ms": adj_ms, "step_ratio": adj_ms / fwd_ms,
             "grad_norm_p0": float(Qg.grad[..., 0].norm()), "grad_norm_c": float(cg.grad.norm())}
 
 

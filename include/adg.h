@@ -96,9 +96,10 @@ typedef struct adg_ctx adg_ctx;
  *   workspace_bytes = device workspace the caller must pass to adg_init: the
  *                     face hull (Theorem 1; Table 1 task extrapolate: one time
  *                     value per face node, or N+1 with cfg->spacetime_traces)
- *                     plus reduction scratch; with cfg->adjoint also a copy
- *                     of Q, the hull's bars and per-block Picard scratch
- *                     (at most 2048 blocks, at most 2 GiB); with cfg->fused a
+ *                     plus reduction scratch; with cfg->adjoint also the
+ *                     hull's bars, per-block scratch of the Picard iterates
+ *                     (at most 2048 blocks, at most 2 GiB) and one material
+ *                     bar slot per cell face; with cfg->fused a
  *                     second Q~ buffer, a second hull and 256 bytes of time
  *                     step state.
  * Any output pointer may be NULL.  Returns INVALID_ARG / UNSUPPORTED as above. */

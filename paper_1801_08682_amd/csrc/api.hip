@@ -20,7 +20,7 @@ thread_local std::string g_err;
 struct Layout {
   int64_t trace_off = 0, trace_bytes = 0;
   int64_t partial_off = 0, partial_count = 0;
-  int64_t qtmp_off = 0, tb_off = 0, slots_off = 0, nslots = 0;
+  int64_t tb_off = 0, slots_off = 0, nslots = 0, pf_off = 0;
   int64_t q2_off = 0, tr2_off = 0, fz_off = 0;   // fused stepping: second Q~, second hull, dt state
   int64_t total = 0;
 };
@@ -113,11 +113,11 @@ Layout layout_of(const adg_config* c, const adg::Launchers* L) {
   if (c->adjoint && L->adjoint) {
     const int R = c->picard_iters > 0 ? c->picard_iters : c->order + 1;
     const int64_t slot = L->adj_slot_doubles(R) * 8;
-    l.qtmp_off = l.total;
-    l.tb_off = l.qtmp_off + align256(cells * L->qdofs_per_cell * 8);
+    l.tb_off = l.total;
     l.slots_off = l.tb_off + align256(cells * L->trace_bytes_per_cell);
     l.nslots = adjoint_slots(cells, slot);
-    l.total = l.slots_off + align256(l.nslots * slot);
+    l.pf_off = l.slots_off + align256(l.nslots * slot);
+    l.total = l.pf_off + align256(cells * L->adj_pf_per_cell * 8);
   }
   if (c->fused) {
     l.q2_off = l.total;
@@ -280,10 +280,10 @@ struct adg_ctx {
     a.n_partial = lay.partial_count - 256;   // the last 256 slots stage the dt reduction
     a.n_partial_used = &n_partial_used;
     if (lay.nslots > 0) {
-      a.adj_qtmp = reinterpret_cast<double*>(ws + lay.qtmp_off);
       a.adj_tb = reinterpret_cast<double*>(ws + lay.tb_off);
       a.adj_slots = reinterpret_cast<double*>(ws + lay.slots_off);
       a.adj_nslots = lay.nslots;
+      a.adj_pf = reinterpret_cast<double*>(ws + lay.pf_off);
     }
     a.ncells = ncells;
     for (int i = 0; i < 3; ++i) {

@@ -358,9 +358,10 @@ struct LaunchArgs {
   double* params_bar = nullptr;     // adjoint accumulator
   int32_t* flag = nullptr;
   void* traces = nullptr;           // face hull
-  double* adj_qtmp = nullptr;       // adjoint: copy of Q for the traces
+  bool traces_only = false;         // predictor: hull only, no Q~ (adjoint replay)
   double* adj_tb = nullptr;         // adjoint: trace bars
   double* adj_slots = nullptr;      // adjoint: per-block Picard scratch
+  double* adj_pf = nullptr;         // adjoint: per (cell, face) material bars
   int64_t adj_nslots = 0;
   double* partial = nullptr;        // per-block maxima
   int64_t n_partial = 0;            // capacity of partial
@@ -388,6 +389,7 @@ struct Launchers {
   LaunchFn fv_step = nullptr;
   int64_t trace_bytes_per_cell = 0;
   int64_t qdofs_per_cell = 0;                  // m (N+1)^d
+  int64_t adj_pf_per_cell = 0;                 // 2d NPAR (adjoint face material bars)
   int64_t (*adj_slot_doubles)(int R) = nullptr;
 };
 

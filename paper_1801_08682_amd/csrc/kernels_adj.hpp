@@ -4,19 +4,21 @@
 // Q~ = u + (dt/h) V(Fbar), traces from the Picard predictor q^R (Sec. 3,
 // Eq. (2)-(6)).  Given G = dJ/dQ+:
 //
-//  k_adj_corr  per cell and face: the face-flux bar
+//  k_adj_face  per face (each owned by its upper cell): the face-flux bar
 //                Fb* = -(dt/h) LR^T G(left cell) + (dt/h) LL^T G(right cell),
 //              its Rusanov transpose (qL, qR, fL, fR bars; the maximum speed
 //              s passes its bar to the first maximal face node, left side
-//              first), written as this cell's own trace bars.  Both cells of
-//              a face compute the face quantities identically; each writes
-//              only its own bars and material bars (no atomics).
+//              first), written as the trace bars of both cells; the
+//              material bars of each side to a per (cell, face) slot.
 //  k_adj_pred  per cell: recompute the Picard iterates (q^1..q^{R-1} kept
 //              in a per-block scratch slot, time columns in registers,
 //              pencils in LDS), map the trace bars and Kv^T G back to bars of
 //              (qbar, Fbar_i), then sweep the iterations backwards:
 //              rhs bar = -(dt/h) P^T qb, F_i bar = D_i^T rhs bar,
 //              q^{r-1} bar = sum_i J_i(q^{r-1})^T F_i bar, u bar += sum_t q^r bar.
+//  k_adj_pred_ck  linear fluxes at the default R = N + 1: the same bars by
+//              the reverse of the power form (below).
+//  Both predictor kernels add the face kernel's material bars of the cell.
 #pragma once
 
 #include "kernels_fwd.hpp"
@@ -30,7 +32,7 @@ struct AdjCorrP {
   const double* dt;
   const double* tr;      // forward traces of Q (float64)
   double* tb;            // trace bars, same layout as the traces
-  double* pbar;          // per-cell material bars (nullable)
+  double* pf;            // per (cell, face) material bars (nullable)
   int64_t ncells;
   int nc[3];
   int brick[3];
@@ -39,20 +41,36 @@ struct AdjCorrP {
   double LL[K::n], LR[K::n];
 };
 
-// Same schedule as the forward corrector: CCPB cells per workgroup, one
-// thread per (face, face node) task, cells taken in the XCD-aware brick walk
-// so the neighbours' G and traces are shared in L2.
+// Workgroup shape of k_adj_face: one thread per (axis, face node) of the
+// cell's lower faces, FCPB cells per workgroup.
 template <class K>
-__global__ void __launch_bounds__(K::CTHREADS) k_adj_corr(const AdjCorrP<K> p) {
+struct AdjFace {
+  static constexpr int FT = K::D * K::NF;
+  static constexpr int FCPB = FT >= 256 ? 1 : 256 / FT;
+  static constexpr int THREADS = FCPB * FT;
+};
+
+// Each face once: a cell takes its d lower faces (between its -e_i
+// neighbour L and itself), so every face of the grid has one owner.  The
+// cell's own G is staged in LDS (its pencils give LL^T G for all d faces);
+// the neighbour's pencils give LR^T G.  Both sides' trace bars are written
+// (the neighbour's upper face and this cell's lower face: each face slot of
+// the trace-bar array has exactly one writer), and the material bars of each
+// side go to a per (cell, face) slot that the predictor's reverse adds in, so
+// no atomics.  Cells in the XCD-aware brick walk of the forward corrector.
+template <class K>
+__global__ void __launch_bounds__(AdjFace<K>::THREADS) k_adj_face(const AdjCorrP<K> p) {
   using PDE = typename K::PDE;
-  constexpr int n = K::n, M = K::M, NF = K::NF, D = K::D, CT = K::CT, NPAR = K::NPAR;
-  constexpr int FT = 2 * D * NF, CC = K::CCPB;
+  constexpr int n = K::n, M = K::M, NF = K::NF, NS = K::NS, D = K::D, NPAR = K::NPAR;
+  constexpr int FT = AdjFace<K>::FT, CC = AdjFace<K>::FCPB, TH = AdjFace<K>::THREADS;
+  __shared__ double Gs[CC][NS * M];
   __shared__ double lamL[CC][FT], lamR[CC][FT], sbp[CC][FT];
-  __shared__ double smax[CC][2 * D], sbar[CC][2 * D];
-  __shared__ int bstar[CC][2 * D], sstar[CC][2 * D];
-  __shared__ double pred[NPAR > 0 ? CC * NPAR * CT : 1];
-  const int lc = threadIdx.x / CT;
-  const int t = threadIdx.x - lc * CT;
+  __shared__ double smax[CC][D], sbar[CC][D];
+  __shared__ int bstar[CC][D], sstar[CC][D];
+  __shared__ int64_t cid[CC];
+  __shared__ double pr[NPAR > 0 ? CC * 2 * NPAR * FT : 1];
+  const int lc = threadIdx.x / FT;
+  const int t = threadIdx.x - lc * FT;
   const double cdt = (*p.dt) * p.inv_h;
   const int64_t groups = (p.ncells + CC - 1) / CC;
   const int64_t grp = xcd_group(groups);
@@ -60,55 +78,53 @@ __global__ void __launch_bounds__(K::CTHREADS) k_adj_corr(const AdjCorrP<K> p) {
   const int64_t gc = grp * CC + lc;
   const bool live = gc < p.ncells;
   const int64_t cell = live ? brick_cell(gc, p.nc, p.brick) : 0;
+  if (t == 0) cid[lc] = live ? cell : -1;
+  __syncthreads();
+  for (int e = threadIdx.x; e < CC * NS * M; e += TH) {
+    const int c = e / (NS * M), r = e - c * (NS * M);
+    if (cid[c] >= 0) Gs[c][r] = p.G[cid[c] * NS * M + r];
+  }
+  __syncthreads();
 
-  double pb[NPAR > 0 ? NPAR : 1];
-#pragma unroll
-  for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
-  double qL[M], qR[M], Fb[M], dq[M];
-  int f = 0, b = 0, i = 0, s = 0;
-  const bool ftask = live && t < FT;
-  if (ftask) {
-    f = t / NF;
-    b = t - f * NF;
-    i = f >> 1;
-    s = f & 1;
-    const int64_t cL = s ? cell : neighbour<K>(cell, i, -1, p.nc);
-    const int64_t cR = s ? neighbour<K>(cell, i, +1, p.nc) : cell;
+  const int i = t / NF, b = t - i * NF;
+  const int64_t cL = live ? neighbour<K>(cell, i, -1, p.nc) : 0;
+  double qL[M], qR[M], Fb[M];
+  const auto pL = PDE::template cell<double>(p.par + cL * NPAR);
+  const auto pR = PDE::template cell<double>(p.par + cell * NPAR);
+  if (live) {
     const double* trL = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::NQ * NF * M + b;
-    const double* trR = p.tr + cR * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b;
+    const double* trR = p.tr + cell * K::TRACE_ELEMS + (int64_t)(2 * i) * K::NQ * NF * M + b;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       qL[v] = trL[v * NF];
       qR[v] = trR[v * NF];
-      dq[v] = qR[v] - qL[v];
       Fb[v] = 0.0;
     }
-    const auto pL = PDE::template cell<double>(p.par + cL * NPAR);
-    const auto pR = PDE::template cell<double>(p.par + cR * NPAR);
     static_for<0, D>([&](auto I_) {
       constexpr int I = decltype(I_)::value;
       if (i == I) {
         lamL[lc][t] = PDE::template speed<I>(qL, p.g, pL);
         lamR[lc][t] = PDE::template speed<I>(qR, p.g, pR);
         // Fb* = -(dt/h) (LR^T G_L)_b + (dt/h) (LL^T G_R)_b
-        const double* GL = p.G + cL * K::NS * M;
-        const double* GR = p.G + cR * K::NS * M;
+        const double* GL = p.G + cL * NS * M;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
           const int nd = pencil_node<n, I>(b, k);
 #pragma unroll
           for (int v = 0; v < M; ++v)
-            Fb[v] += -cdt * p.LR[k] * GL[nd * M + v] + cdt * p.LL[k] * GR[nd * M + v];
+            Fb[v] += -cdt * p.LR[k] * GL[nd * M + v] + cdt * p.LL[k] * Gs[lc][nd * M + v];
         }
       }
     });
     double sp = 0.0;
 #pragma unroll
-    for (int v = 0; v < M; ++v) sp += Fb[v] * dq[v];
+    for (int v = 0; v < M; ++v) sp += Fb[v] * (qR[v] - qL[v]);
     sbp[lc][t] = -0.5 * sp;
   }
   __syncthreads();
-  if (live && t < 2 * D) {
+  if (live && t < D) {
+    // the largest speed of face t and the first node that attains it (left
+    // side before right), and the bar of that speed
     double best = -1.0, acc = 0.0;
     int bs = 0, ss = 0;
     for (int bb = 0; bb < NF; ++bb) {
@@ -123,42 +139,58 @@ __global__ void __launch_bounds__(K::CTHREADS) k_adj_corr(const AdjCorrP<K> p) {
     sbar[lc][t] = acc;
   }
   __syncthreads();
-  if (ftask) {
-    // this cell is the left state of its right face (s = 1) and the right
-    // state of its left face (s = 0)
-    double tq[M], tf[M], own[M];
-    const double sgn = s ? 0.5 : -0.5;
+  double pbs[2][NPAR > 0 ? NPAR : 1];
 #pragma unroll
-    for (int v = 0; v < M; ++v) {
-      own[v] = s ? qL[v] : qR[v];
-      tq[v] = sgn * smax[lc][f] * Fb[v];
-      tf[v] = 0.5 * Fb[v];
-    }
-    const auto pc = PDE::template cell<double>(p.par + cell * NPAR);
-    const bool mine = (bstar[lc][f] == b) && (sstar[lc][f] == (s ? 0 : 1));
-    static_for<0, D>([&](auto I_) {
-      constexpr int I = decltype(I_)::value;
-      if (i == I) {
-        if (mine) PDE::template speed_adj<I>(own, sbar[lc][f], tq, pb, p.g, pc);
-        if constexpr (K::NQ == 1) PDE::template flux_adj<I>(own, tf, tq, pb, p.g, pc);
+  for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+    for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pbs[sd][k] = 0.0;
+  if (live) {
+    // side 0: this cell, the right state of the face (its lower face 2i);
+    // side 1: the neighbour, the left state (its upper face 2i + 1)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      double tq[M], tf[M];
+      const double sgn = sd ? 0.5 : -0.5;
+      const double* own = sd ? qL : qR;
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        tq[v] = sgn * smax[lc][i] * Fb[v];
+        tf[v] = 0.5 * Fb[v];
       }
-    });
-    double* out = p.tb + cell * K::TRACE_ELEMS + (int64_t)f * K::NQ * NF * M + b;
+      const auto& po = sd ? pL : pR;
+      const bool mine = (bstar[lc][i] == b) && (sstar[lc][i] == (sd ? 0 : 1));
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        if (i == I) {
+          if (mine) PDE::template speed_adj<I>(own, sbar[lc][i], tq, pbs[sd], p.g, po);
+          if constexpr (K::NQ == 1) PDE::template flux_adj<I>(own, tf, tq, pbs[sd], p.g, po);
+        }
+      });
+      const int64_t oc = sd ? cL : cell;
+      double* out = p.tb + oc * K::TRACE_ELEMS + (int64_t)(2 * i + sd) * K::NQ * NF * M + b;
 #pragma unroll
-    for (int v = 0; v < M; ++v) out[v * NF] = tq[v];
-    if constexpr (K::NQ == 2) {
+      for (int v = 0; v < M; ++v) out[v * NF] = tq[v];
+      if constexpr (K::NQ == 2) {
 #pragma unroll
-      for (int v = 0; v < M; ++v) out[NF * M + v * NF] = tf[v];
+        for (int v = 0; v < M; ++v) out[NF * M + v * NF] = tf[v];
+      }
     }
   }
   if constexpr (NPAR > 0) {
 #pragma unroll
-    for (int k = 0; k < NPAR; ++k) pred[(lc * NPAR + k) * CT + t] = pb[k];
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int k = 0; k < NPAR; ++k) pr[((lc * 2 + sd) * NPAR + k) * FT + t] = pbs[sd][k];
     __syncthreads();
-    if (live && t < NPAR && p.pbar) {
-      double acc = 0.0;
-      for (int j = 0; j < CT; ++j) acc += pred[(lc * NPAR + t) * CT + j];
-      p.pbar[cell * NPAR + t] += acc;
+    if (live && p.pf) {
+      for (int u = t; u < 2 * D * NPAR; u += FT) {
+        const int sd = u / (D * NPAR), rem = u - sd * (D * NPAR);
+        const int fi = rem / NPAR, k = rem - fi * NPAR;
+        double acc = 0.0;
+        for (int bb = 0; bb < NF; ++bb) acc += pr[((lc * 2 + sd) * NPAR + k) * FT + fi * NF + bb];
+        const int64_t oc = sd ? neighbour<K>(cell, fi, -1, p.nc) : cell;
+        p.pf[(oc * 2 * D + 2 * fi + sd) * NPAR + k] = acc;
+      }
     }
   }
 }
@@ -171,6 +203,7 @@ struct AdjPredP {
   double* Qbar;          // in: dJ/dQ+, out: dJ/dQ
   const double* tb;      // trace bars
   double* pbar;
+  const double* pf;      // per (cell, face) material bars of the face kernel
   double* scratch;       // per-block slots of stored Picard iterates
   int64_t slot_doubles;
   int64_t ncells;
@@ -199,6 +232,7 @@ struct AdjPlan {
 // [r-1][t][v][CPB * NS], node fastest (coalesced per thread).
 template <class K>
 constexpr int64_t adj_slot_doubles(int R) {
+  if (K::CK && R == K::N + 1) return (int64_t)R * K::M * K::NS * K::CPB;   // k_adj_pred_ck
   const int64_t levels = R > 2 ? R - 1 : 1;
   return levels * K::n * K::M * K::NS * K::CPB;
 }
@@ -491,6 +525,7 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
       if (a < NPAR && live && p.pbar) {
         double acc = 0.0;
         for (int j = 0; j < NS; ++j) acc += pred[(lc * NPAR + a) * NS + j];
+        for (int f = 0; f < 2 * D; ++f) acc += p.pf[(cell * 2 * D + f) * NPAR + a];
         p.pbar[cell * NPAR + a] += acc;
       }
     }
@@ -498,18 +533,229 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
   }
 }
 
-// Reverse of one step: Qtmp <- Q; forward predictor on Qtmp (float64 traces
-// of Q); k_adj_corr; k_adj_pred.  Workspace: traces, trace bars, Qtmp, slots.
+// Linear fluxes (the power form of the forward predictor, see pred_cell): the
+// time average is qbar = z_0 of the Horner recursion z_R = a_R u,
+// z_k = a_k u + L z_{k+1}, a_k = (-dt/h)^k w.T_k (T_0 = 1, T_k = P^{k-1} Ps),
+// L = sum_i D_i F_i.  Per cell:
+//  1. forward Horner: R gathers of L; z_1..z_R go to the block's scratch slot
+//     when material bars are wanted (they are the states of the bilinear
+//     material terms; the Jacobians themselves do not depend on the state);
+//  2. bars of qbar and Fbar_i = F_i(qbar) from the trace bars and Kv^T G, as
+//     in k_adj_pred; zbar_0 = qbar bar + sum_i J_i^T Fbar_i bar;
+//  3. reverse Horner: u bar += a_k zbar_k, zbar_{k+1} = L^T zbar_k,
+//     params bar += (d(L z_{k+1})/d params)^T zbar_k; u bar += a_R zbar_R.
+// L^T y = sum_i J_i^T (D_i^T y), gathered along the d pencils through each
+// node.  No Picard iterates and no time slices: 2R gathers of one field
+// against R sweeps over n slices.  Used for R = N + 1 (the default).
+template <class K>
+__global__ void __launch_bounds__(K::NODE_THREADS) __attribute__((amdgpu_waves_per_eu(2))) k_adj_pred_ck(const AdjPredP<K> p) {
+  using PDE = typename K::PDE;
+  constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, NPAR = K::NPAR;
+  constexpr int CPB = K::CPB, NSP = K::NSP, RR = K::N + 1;
+  constexpr int CELLD = D * NSP * K::MP;                  // doubles of LDS per cell
+  // z_1..z_R of the material terms in LDS when they fit beside the gather
+  // planes, else in the block's scratch slot
+  constexpr int ZD = RR * M * NS * CPB;
+  constexpr bool ZLDS = NPAR > 0 && (CPB * CELLD + ZD) * 8 <= 48 * 1024;
+  static_assert(NPAR * NS <= CELLD, "material bars reuse the gather planes");
+  __shared__ __align__(16) double smem[CPB * CELLD + (ZLDS ? ZD : 0)];
+  __shared__ double s_al[RR + 1];
+  __shared__ double s_D[n][n];           // in LDS: read inside the loops, not held live
+  double* pred = smem;
+  const int lc = threadIdx.x / NS;
+  const int a = threadIdx.x - lc * NS;
+  double* Fs = smem + lc * CELLD;                          // [axis][var][node] planes
+  const double c = (*p.dt) * p.inv_h;
+  for (int i = threadIdx.x; i < n * n; i += K::NODE_THREADS) s_D[i / n][i % n] = p.t.D[i / n][i % n];
+  if (threadIdx.x == 0) {
+    // a_k for k = 0..R (R = N + 1), uniform over the grid
+    double T[n], ck = 1.0;
+    for (int t = 0; t < n; ++t) T[t] = p.t.Ps[t];
+    s_al[0] = 1.0;
+    for (int k = 1; k <= RR; ++k) {
+      if (k > 1) {
+        double Tn[n];
+        for (int t = 0; t < n; ++t) {
+          double s = 0.0;
+          for (int tt = 0; tt < n; ++tt) s = fma(p.t.P[t][tt], T[tt], s);
+          Tn[t] = s;
+        }
+        for (int t = 0; t < n; ++t) T[t] = Tn[t];
+      }
+      ck *= -c;
+      double beta = 0.0;
+      for (int t = 0; t < n; ++t) beta = fma(p.t.w[t], T[t], beta);
+      s_al[k] = ck * beta;
+    }
+  }
+  __syncthreads();
+  // z_k of this thread's node in the block's slot: [k-1][var][thread]
+  const bool keep = NPAR > 0 && p.pbar != nullptr;
+  double* zs = (ZLDS ? smem + CPB * CELLD : p.scratch + (int64_t)blockIdx.x * p.slot_doubles) + threadIdx.x;
+  auto zat = [&](int k, int v) -> double& { return zs[((int64_t)(k - 1) * M + v) * (CPB * NS)]; };
+
+  for (int64_t c0 = (int64_t)blockIdx.x * CPB; c0 < p.ncells; c0 += (int64_t)gridDim.x * CPB) {
+    const int64_t cell = c0 + lc;
+    const bool live = cell < p.ncells;
+    const int64_t cs = live ? cell : 0;
+    double u[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) u[v] = p.Q[(cs * NS + a) * M + v];
+    const auto cp = PDE::template cell<double>(p.par + cs * NPAR);
+    double pb[NPAR > 0 ? NPAR : 1];
+#pragma unroll
+    for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
+
+    // z <- a_k u + L z (every node thread gives its z)
+    double z[M];
+    auto horner = [&](int k) {
+      __syncthreads();                                    // earlier readers of Fs done
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        double F[M];
+        PDE::template flux<I>(z, F, p.g, cp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + K::slot(a), v)] = F[v];
+      });
+      __syncthreads();
+      const double ak = s_al[k];
+#pragma unroll
+      for (int v = 0; v < M; ++v) z[v] = ak * u[v];
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        constexpr int sI = K::sstride(I);
+        __builtin_amdgcn_sched_barrier(0);               // one pencil's loads live at a time
+        const int ai = coord<n, I>(a);
+        const int e0 = I * NSP + K::slot(a) - ai * sI;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const double dj = s_D[ai][j];
+#pragma unroll
+          for (int v = 0; v < M; ++v) z[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], z[v]);
+        }
+      });
+    };
+    // zb <- L^T zb with the state zk of the material terms; u bar += a_k zb first
+    double zb[M], ub[M];
+    auto horner_rev = [&](int k, const double (&zk)[M]) {
+      const double ak = s_al[k];
+#pragma unroll
+      for (int v = 0; v < M; ++v) ub[v] = fma(ak, zb[v], ub[v]);
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(K::slot(a), v)] = zb[v];
+      __syncthreads();
+      double nz[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) nz[v] = 0.0;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        constexpr int sI = K::sstride(I);
+        __builtin_amdgcn_sched_barrier(0);
+        const int ai = coord<n, I>(a);
+        const int e0 = K::slot(a) - ai * sI;
+        double g[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) g[v] = 0.0;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const double dj = s_D[j][ai];
+#pragma unroll
+          for (int v = 0; v < M; ++v) g[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], g[v]);
+        }
+        PDE::template flux_adj<I>(zk, g, nz, pb, p.g, cp);
+      });
+#pragma unroll
+      for (int v = 0; v < M; ++v) zb[v] = nz[v];
+    };
+
+    // ---- 1. forward Horner: z_R = a_R u, then down to z_0 = qbar ----
+#pragma unroll
+    for (int v = 0; v < M; ++v) z[v] = s_al[RR] * u[v];
+#pragma unroll 1
+    for (int k = RR - 1; k >= 0; --k) {
+      if (keep) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) zat(k + 1, v) = z[v];
+      }
+      horner(k);
+    }
+
+    // ---- 2. bars of qbar = z_0 and Fbar_i at this node ----
+    const double* TB = p.tb + cs * K::TRACE_ELEMS;
+    const double* Gc = p.Qbar + cs * NS * M;
+#pragma unroll
+    for (int v = 0; v < M; ++v) zb[v] = 0.0;
+    static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      __builtin_amdgcn_sched_barrier(0);                 // one axis's loads live at a time
+      const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
+      const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb;
+      const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb;
+      double Fbb[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        zb[v] += p.t.FL[ai] * tl[v * NF] + p.t.FR[ai] * trr[v * NF];
+        Fbb[v] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const int nd = pencil_node<n, I>(fb, k);
+        const double kv = c * p.t.Kv[k][ai];
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fbb[v] += kv * Gc[nd * M + v];
+      }
+      PDE::template flux_adj<I>(z, Fbb, zb, pb, p.g, cp);
+    });
+#pragma unroll
+    for (int v = 0; v < M; ++v) ub[v] = Gc[a * M + v];
+
+    // ---- 3. reverse Horner ----
+#pragma unroll 1
+    for (int k = 0; k < RR; ++k) {
+      double zk[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) zk[v] = keep ? zat(k + 1, v) : 0.0;   // only material terms read it
+      horner_rev(k, zk);
+    }
+    {
+      const double aR = s_al[RR];
+#pragma unroll
+      for (int v = 0; v < M; ++v) ub[v] = fma(aR, zb[v], ub[v]);
+    }
+    __syncthreads();                       // every read of this cell's G and Fs is done
+    if (live) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) p.Qbar[(cell * NS + a) * M + v] = ub[v];
+    }
+    if constexpr (NPAR > 0) {
+#pragma unroll
+      for (int k = 0; k < NPAR; ++k) pred[(lc * NPAR + k) * NS + a] = pb[k];
+      __syncthreads();
+      if (a < NPAR && live && p.pbar) {
+        double acc = 0.0;
+        for (int j = 0; j < NS; ++j) acc += pred[(lc * NPAR + a) * NS + j];
+        for (int f = 0; f < 2 * D; ++f) acc += p.pf[(cell * 2 * D + f) * NPAR + a];
+        p.pbar[cell * NPAR + a] += acc;
+      }
+    }
+    __syncthreads();                       // LDS reused by the next cell
+  }
+}
+
+// Reverse of one step: forward predictor of Q for its float64 traces (no Q~
+// written, Q untouched); k_adj_face; k_adj_pred or k_adj_pred_ck.  Workspace:
+// traces, trace bars, slots, per (cell, face) material bars.
 template <class K>
 int launch_adjoint(const LaunchArgs& a) {
   static_assert(std::is_same<typename K::Real, double>::value, "adjoint is float64");
-  const int64_t qbytes = a.ncells * K::NS * K::M * 8;
-  hipError_t e = hipMemcpyAsync(a.adj_qtmp, a.Qc, qbytes, hipMemcpyDeviceToDevice, a.stream);
-  if (e != hipSuccess) return (int)e;
+  // forward traces of Q (the hull only: Q is read, nothing else written)
   LaunchArgs f = a;
-  f.Q = a.adj_qtmp;
+  f.qin = a.Qc;
+  f.traces_only = true;
   int st = launch_predict<K>(f);
   if (st) return st;
+  hipError_t e;
 
   AdjCorrP<K> pc;
   pc.G = a.Qbar;
@@ -517,7 +763,7 @@ int launch_adjoint(const LaunchArgs& a) {
   pc.dt = a.dt;
   pc.tr = reinterpret_cast<const double*>(a.traces);
   pc.tb = a.adj_tb;
-  pc.pbar = a.params_bar;
+  pc.pf = a.params_bar ? a.adj_pf : nullptr;
   pc.ncells = a.ncells;
   for (int k = 0; k < 3; ++k) pc.nc[k] = a.nc[k];
   pc.inv_h = a.inv_h;
@@ -527,9 +773,9 @@ int launch_adjoint(const LaunchArgs& a) {
     pc.LR[k] = a.tab->LR[k];
   }
   for (int k = 0; k < 3; ++k) pc.brick[k] = a.brick[k];
-  const int64_t groups = (a.ncells + K::CCPB - 1) / K::CCPB;
+  const int64_t groups = (a.ncells + AdjFace<K>::FCPB - 1) / AdjFace<K>::FCPB;
   const int64_t Gc = 8 * ((groups + 7) / 8);
-  hipLaunchKernelGGL(k_adj_corr<K>, dim3((unsigned)Gc), dim3(K::CTHREADS), 0, a.stream, pc);
+  hipLaunchKernelGGL(k_adj_face<K>, dim3((unsigned)Gc), dim3(AdjFace<K>::THREADS), 0, a.stream, pc);
   e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
 
@@ -540,6 +786,7 @@ int launch_adjoint(const LaunchArgs& a) {
   pp.Qbar = a.Qbar;
   pp.tb = a.adj_tb;
   pp.pbar = a.params_bar;
+  pp.pf = a.adj_pf;
   pp.scratch = a.adj_slots;
   pp.slot_doubles = adj_slot_doubles<K>(a.R);
   pp.ncells = a.ncells;
@@ -547,6 +794,26 @@ int launch_adjoint(const LaunchArgs& a) {
   pp.R = a.R;
   for (int k = 0; k < 4; ++k) pp.g.c[k] = a.gp[k];
   pp.t = make_ktab<K::n, double>(*a.tab);
+  if constexpr (K::CK) {
+    if (a.R == K::N + 1) {
+      // linear flux, default R: the reverse of the power form
+      static int resident_ck = 0;
+      if (resident_ck == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+          e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_pred_ck<K>, K::NODE_THREADS, 0);
+        if (e != hipSuccess) return (int)e;
+        resident_ck = cus * (per_cu > 0 ? per_cu : 1);
+      }
+      int64_t G = (a.ncells + K::CPB - 1) / K::CPB;
+      if (G > a.adj_nslots) G = a.adj_nslots;
+      if (G > resident_ck) G = resident_ck;
+      hipLaunchKernelGGL(k_adj_pred_ck<K>, dim3((unsigned)G), dim3(K::NODE_THREADS), 0, a.stream, pp);
+      return (int)hipGetLastError();
+    }
+  }
   // Persistent blocks: no more than fit on the device at once, so every
   // block starts together and walks the same number of cells.
   static int resident = 0;

@@ -202,7 +202,7 @@ __device__ __forceinline__ int task_e0(int a) {
 template <class K>
 struct PredP {
   const double* Qin;     // Q (cell, node, var)
-  double* Qout;          // Q~ = Q + dt V; may be Qin
+  double* Qout;          // Q~ = Q + dt V; may be Qin; null: traces only
   const double* par;
   const double* dt;
   typename K::Real* tr;
@@ -639,7 +639,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     }
     __syncthreads();
   });
-  if (live && node) {
+  if (live && node && p.Qout) {
 #pragma unroll
     for (int v = 0; v < M; ++v) p.Qout[(cell * NS + a) * M + v] = u[v] + cdt * Vs[v * NS + a];
   }
@@ -1146,7 +1146,7 @@ PredP<K> pred_params(const LaunchArgs& a) {
   using Real = typename K::Real;
   PredP<K> p;
   p.Qin = a.qin ? a.qin : a.Q;
-  p.Qout = a.qout ? a.qout : a.Q;
+  p.Qout = a.traces_only ? nullptr : (a.qout ? a.qout : a.Q);
   p.par = a.params;
   p.dt = a.dt;
   p.tr = reinterpret_cast<Real*>(a.traces);
@@ -1259,6 +1259,7 @@ Launchers make_fwd_launchers() {
   L.fused = &launch_fused<K>;
   L.trace_bytes_per_cell = K::TRACE_ELEMS * (int64_t)sizeof(typename K::Real);
   L.qdofs_per_cell = (int64_t)K::NS * K::M;
+  L.adj_pf_per_cell = (int64_t)2 * K::D * K::NPAR;
   return L;
 }
 

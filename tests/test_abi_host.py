@@ -128,9 +128,10 @@ def test_product_path_has_no_oracle_dependency():
 
 @pytest.mark.parametrize("name", ["C4", "C5"])
 def test_query_adjoint_workspace(L, name):
-    """The adjoint adds a copy of Q, the hull's bars and per-block slots that
-    hold the Picard iterates q^1..q^{R-1} of one block's cells (at most 2048
-    blocks and 2 GiB)."""
+    """The adjoint adds the hull's bars, per-block slots (at most
+    2048 blocks and 2 GiB) and one material-bar slot per cell face.  A slot
+    holds the Picard iterates q^1..q^{R-1} of one block's cells, or for a
+    linear flux at R = N + 1 the Horner states z_1..z_R (R m values per node)."""
     wl = inputs.preset(name)
     _, _, w = _lib.query(cfg_of(wl))
     c = cfg_of(wl)
@@ -140,10 +141,12 @@ def test_query_adjoint_workspace(L, name):
     ns = n ** d
     R = wl.picard_iters or wl.order + 1
     cpb = 1 if ns >= 128 else 128 // ns
-    slot = max(R - 1, 1) * n * m * ns * cpb * 8
+    linear = wl.pde != inputs.EULER
+    slot = (R * m if linear and R == wl.order + 1 else max(R - 1, 1) * n * m) * ns * cpb * 8
     nslots = min(wl.ncells, 2048, (2 << 30) // slot)
     nq = 2 if wl.pde == inputs.EULER else 1
-    extra = wl.ncells * m * ns * 8 + wl.ncells * 2 * d * nq * m * n ** (d - 1) * 8 + nslots * slot
+    extra = (wl.ncells * 2 * d * nq * m * n ** (d - 1) * 8 + nslots * slot
+             + wl.ncells * 2 * d * wl.npar * 8)
     assert extra <= wa - w <= extra + 3 * 256
     assert nslots * slot <= 2 << 30
     c.precision = inputs.FP32

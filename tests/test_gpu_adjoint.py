@@ -56,6 +56,41 @@ def test_step_vjp_matches_oracle_autograd(case):
     st.close()
 
 
+@pytest.mark.parametrize("pde,d,N,nc,R", [(inputs.ACOUSTIC, 3, 3, (2, 2, 3), 2),
+                                          (inputs.ELASTIC, 2, 3, (3, 2), 3)])
+def test_linear_vjp_other_picard_counts_and_no_material_bars(pde, d, N, nc, R):
+    """Linear fluxes take the power-form adjoint for the default count R = N + 1
+    and the stored-iterate adjoint otherwise: both against the oracle's
+    autograd at the same R; without a material-bar buffer the state bar is
+    unchanged (bitwise)."""
+    wl = _wl(pde, d, N, nc).with_(picard_iters=R)
+    Q = inputs.random_state(wl, seed=31, amplitude=0.05)
+    par = inputs.cell_params(wl, seed=3)
+    G = np.random.default_rng(9).standard_normal(Q.shape)
+    dt = 2e-3
+    print("case vjp R", pde, d, N, R, flush=True)
+    gq, gp = oadj.step_vjp(torch.tensor(Q), torch.tensor(par), dt, setup_of(wl), torch.tensor(G))
+    st = Stepper(wl, adjoint=True)
+    Qd, pd = torch.tensor(Q, device="cuda"), torch.tensor(par, device="cuda")
+    Gd = torch.tensor(G, device="cuda")
+    pbar = torch.zeros_like(pd)
+    st.step_adjoint(Qd, pd, st.scalar(dt), Gd, pbar)
+    torch.cuda.synchronize()
+    assert float((Gd.cpu() - gq).norm() / gq.norm()) < 1e-11
+    assert float((pbar.cpu() - gp).norm() / gp.norm()) < 1e-11
+    st.close()
+    wl1 = wl.with_(picard_iters=0)
+    gq1, _ = oadj.step_vjp(torch.tensor(Q), torch.tensor(par), dt, setup_of(wl1), torch.tensor(G))
+    st = Stepper(wl1, adjoint=True)
+    G1, G2 = torch.tensor(G, device="cuda"), torch.tensor(G, device="cuda")
+    st.step_adjoint(Qd, pd, st.scalar(dt), G1, torch.zeros_like(pd))
+    st.step_adjoint(Qd, pd, st.scalar(dt), G2, None)
+    torch.cuda.synchronize()
+    assert torch.equal(G1, G2)
+    assert float((G1.cpu() - gq1).norm() / gq1.norm()) < 1e-11
+    st.close()
+
+
 def test_step_vjp_central_differences():
     """<dJ/dQ, v> against (J(Q + e v) - J(Q - e v)) / 2e for J = <G, S(Q)>,
     on 4 seeded directions (GPU forward only)."""
