@@ -96,7 +96,10 @@ typedef struct adg_ctx adg_ctx;
  *   workspace_bytes = device workspace the caller must pass to adg_init: the
  *                     face hull (Theorem 1; Table 1 task extrapolate: one time
  *                     value per face node, or N+1 with cfg->spacetime_traces)
- *                     plus reduction scratch; with cfg->adjoint also the
+ *                     plus reduction scratch; with cfg->spacetime_traces also
+ *                     the time-integrated Rusanov fluxes of every cell's d
+ *                     lower faces (the corrector's first pass); with
+ *                     cfg->adjoint also the
  *                     hull's bars, per-block scratch of the Picard iterates
  *                     (at most 2048 blocks, at most 2 GiB) and one material
  *                     bar slot per cell face; with cfg->fused a

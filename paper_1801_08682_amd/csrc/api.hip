@@ -21,6 +21,7 @@ struct Layout {
   int64_t trace_off = 0, trace_bytes = 0;
   int64_t partial_off = 0, partial_count = 0;
   int64_t tb_off = 0, slots_off = 0, nslots = 0, pf_off = 0;
+  int64_t stf_off = -1;
   int64_t q2_off = 0, tr2_off = 0, fz_off = 0;   // fused stepping: second Q~, second hull, dt state
   int64_t total = 0;
 };
@@ -110,6 +111,10 @@ Layout layout_of(const adg_config* c, const adg::Launchers* L) {
   // plus 256 slots for the first stage of the dt reduction
   l.partial_count = (cells + 64 > adg::kMaxReduceBlocks ? cells + 64 : adg::kMaxReduceBlocks) + 256;
   l.total = l.partial_off + align256(l.partial_count * 8);
+  if (L->st_face_per_cell > 0) {      // space-time traces: F* of the lower faces
+    l.stf_off = l.total;
+    l.total = l.stf_off + align256(cells * L->st_face_per_cell * 8);
+  }
   if (c->adjoint && L->adjoint) {
     const int R = c->picard_iters > 0 ? c->picard_iters : c->order + 1;
     const int64_t slot = L->adj_slot_doubles(R) * 8;
@@ -279,6 +284,7 @@ struct adg_ctx {
     a.partial = reinterpret_cast<double*>(ws + lay.partial_off);
     a.n_partial = lay.partial_count - 256;   // the last 256 slots stage the dt reduction
     a.n_partial_used = &n_partial_used;
+    if (lay.stf_off >= 0) a.st_face = reinterpret_cast<double*>(ws + lay.stf_off);
     if (lay.nslots > 0) {
       a.adj_tb = reinterpret_cast<double*>(ws + lay.tb_off);
       a.adj_slots = reinterpret_cast<double*>(ws + lay.slots_off);

@@ -359,6 +359,7 @@ struct LaunchArgs {
   int32_t* flag = nullptr;
   void* traces = nullptr;           // face hull
   bool traces_only = false;         // predictor: hull only, no Q~ (adjoint replay)
+  double* st_face = nullptr;        // space-time corrector: F* of the lower faces
   double* adj_tb = nullptr;         // adjoint: trace bars
   double* adj_slots = nullptr;      // adjoint: per-block Picard scratch
   double* adj_pf = nullptr;         // adjoint: per (cell, face) material bars
@@ -390,6 +391,7 @@ struct Launchers {
   int64_t trace_bytes_per_cell = 0;
   int64_t qdofs_per_cell = 0;                  // m (N+1)^d
   int64_t adj_pf_per_cell = 0;                 // 2d NPAR (adjoint face material bars)
+  int64_t st_face_per_cell = 0;                // d (N+1)^(d-1) m (space-time corrector)
   int64_t (*adj_slot_doubles)(int R) = nullptr;
 };
 

@@ -748,6 +748,8 @@ struct CorrP {
   Gconst<double> g;
   double LL[K::n], LR[K::n];
   double w[K::n];        // Gauss-Legendre weights (time integral of space-time fluxes)
+  double* stf;           // space-time traces, two-pass corrector: time-integrated
+                         // F* of every cell's d lower faces [cell][i][var][b]
 };
 
 // Cell visited at position g of a brick-major walk of the grid (bricks of
@@ -1039,6 +1041,191 @@ __global__ void __launch_bounds__(K::CTHREADS) k_corr(const CorrP<K> p) {
   if (bad && p.flag) atomicOr(p.flag, bad);
 }
 
+// Space-time traces, two passes: every face's time-integrated Rusanov flux
+// once, then the update.  A single corrector pass reads each hull face twice
+// (from both of its cells), and at N+1 time values per face node the hull is
+// too large for the second read to find it in L2.
+//  k_st_face   a cell takes its d lower faces (its -e_i neighbour's upper
+//              face and its own lower face): per face node the time loop
+//              of corr_cell's space-time branch (speeds per time node, the
+//              time integral of the mean flux, the jumps in registers), the
+//              maxima over the face nodes per time node, then
+//              F* = sum_t w_t ((fL + fR) / 2 - s_t (qR - qL) / 2), written to
+//              stf[cell][i][var][b].  Same operands and order as corr_cell,
+//              so the result is the same bit for bit.
+//  k_st_update one thread per node: Q~ minus the lifted F* of the node's 2d
+//              faces (the lower ones from the cell's own slot, the upper ones
+//              from the +e_i neighbours', staged in LDS with coalesced
+//              loads), then the speed maxima and flags of the new state as
+//              k_corr.
+template <class K>
+struct StFace {
+  static constexpr int FT = K::D * K::NF;
+  static constexpr int FCPB = FT >= 256 ? 1 : 256 / FT;
+  static constexpr int THREADS = FCPB * FT;
+  static constexpr int UCPB = K::NS >= 256 ? 1 : 256 / K::NS;
+  static constexpr int UTHREADS = UCPB * K::NS;
+};
+
+template <class K>
+__global__ void __launch_bounds__(StFace<K>::THREADS) k_st_face(const CorrP<K> p) {
+  using PDE = typename K::PDE;
+  using Real = typename K::Real;
+  constexpr int M = K::M, NF = K::NF, D = K::D, NT = K::NT;
+  constexpr int FT = StFace<K>::FT, CC = StFace<K>::FCPB;
+  __shared__ double lam[CC][D * NT * NF];
+  __shared__ double sm[CC][D * NT];
+  const int lc = threadIdx.x / FT;
+  const int t = threadIdx.x - lc * FT;
+  const int64_t groups = (p.ncells + CC - 1) / CC;
+  const int64_t grp = xcd_group(groups);
+  if (grp >= groups) return;                    // whole workgroup leaves together
+  const int64_t gc = grp * CC + lc;
+  const bool live = gc < p.ncells;
+  const int64_t cell = live ? brick_cell(gc, p.nc, p.brick) : 0;
+  const int i = t / NF, b = t - i * NF;
+  int bad = 0;
+  double acc[M], dq[NT][M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) acc[v] = 0.0;
+  if (live) {
+    const int64_t cL = neighbour<K>(cell, i, -1, p.nc);
+    const auto pL = PDE::template cell<double>(p.par + cL * K::NPAR);
+    const auto pR = PDE::template cell<double>(p.par + cell * K::NPAR);
+    const Real* trL0 = p.tr + cL * K::TRACE_ELEMS + (int64_t)(2 * i + 1) * K::TFACE + b;
+    const Real* trR0 = p.tr + cell * K::TRACE_ELEMS + (int64_t)(2 * i) * K::TFACE + b;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const Real* trL = trL0 + (int64_t)tt * K::NQ * NF * M;
+      const Real* trR = trR0 + (int64_t)tt * K::NQ * NF * M;
+      double qL[M], qR[M], fL[M], fR[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        qL[v] = (double)trL[v * NF];
+        qR[v] = (double)trR[v * NF];
+        if constexpr (K::NQ == 2) {
+          fL[v] = (double)trL[NF * M + v * NF];
+          fR[v] = (double)trR[NF * M + v * NF];
+        }
+      }
+      double l = 0.0;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        if (i == I) {
+          if constexpr (K::NQ == 1) {
+            PDE::template flux<I>(qL, fL, p.g, pL);
+            PDE::template flux<I>(qR, fR, p.g, pR);
+          }
+          l = fmax(PDE::template speed<I>(qL, p.g, pL), PDE::template speed<I>(qR, p.g, pR));
+        }
+      });
+      if (!(l >= 0.0)) bad |= 2;
+      lam[lc][(i * NT + tt) * NF + b] = l;
+      const double hw = 0.5 * p.w[tt];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        acc[v] += hw * (fL[v] + fR[v]);
+        dq[tt][v] = qR[v] - qL[v];
+        asm volatile("" : "+v"(acc[v]), "+v"(dq[tt][v]));
+      }
+      __builtin_amdgcn_sched_barrier(0);       // one time node's loads at a time
+    }
+  }
+  __syncthreads();
+  for (int ft = t; ft < D * NT; ft += FT) {
+    if (live) {
+      double sv = 0.0;
+      for (int bb = 0; bb < NF; ++bb) sv = fmax(sv, lam[lc][ft * NF + bb]);
+      sm[lc][ft] = sv;
+    }
+  }
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const double hs = 0.5 * p.w[tt] * sm[lc][i * NT + tt];
+#pragma unroll
+      for (int v = 0; v < M; ++v) acc[v] -= hs * dq[tt][v];
+    }
+    double* out = p.stf + ((cell * D + i) * M) * NF + b;
+#pragma unroll
+    for (int v = 0; v < M; ++v) out[v * NF] = acc[v];
+  }
+  if (bad && p.flag) atomicOr(p.flag, bad);
+}
+
+template <class K>
+__global__ void __launch_bounds__(StFace<K>::UTHREADS) k_st_update(const CorrP<K> p) {
+  using PDE = typename K::PDE;
+  constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D;
+  constexpr int CC = StFace<K>::UCPB, TH = StFace<K>::UTHREADS;
+  constexpr int FB = M * NF;                      // one face's F*, contiguous in stf
+  // the cell's 2d faces staged with coalesced loads: [lc][2i + s][var][b]
+  __shared__ double Fs[CC][2 * D * FB];
+  __shared__ int64_t cid[CC];
+  __shared__ double red[(TH + 63) / 64];
+  const int lc = threadIdx.x / NS;
+  const int a = threadIdx.x - lc * NS;
+  const int64_t groups = (p.ncells + CC - 1) / CC;
+  double lmax = 0.0;
+  int bad = 0;
+  const int64_t grp = xcd_group(groups);
+  if (grp < groups) {                       // uniform over the workgroup
+    const int64_t gc = grp * CC + lc;
+    const bool live = gc < p.ncells;
+    const int64_t cell = live ? brick_cell(gc, p.nc, p.brick) : 0;
+    if (a == 0) cid[lc] = live ? cell : -1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < CC * 2 * D * FB; e += TH) {
+      const int c = e / (2 * D * FB), r = e - c * (2 * D * FB);
+      const int f = r / FB, k = r - f * FB;
+      const int i = f >> 1;
+      const int64_t cc = cid[c];
+      if (cc >= 0) {
+        const int64_t src = (f & 1) ? neighbour<K>(cc, i, +1, p.nc) : cc;
+        Fs[c][r] = p.stf[(src * D + i) * FB + k];
+      }
+    }
+    double Qn[M];
+    if (live) {
+      const double* Qp = p.Qin + (cell * NS + a) * M;
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qn[v] = Qp[v];
+    }
+    __syncthreads();
+    if (live) {
+      const double cdt = (*p.dt) * p.inv_h;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        const int k = coord<n, I>(a);
+        const int b = face_node<n, I>(a);
+        const double* Fm = &Fs[lc][(2 * I) * FB + b];
+        const double* Fp = &Fs[lc][(2 * I + 1) * FB + b];
+        const double lr = p.LR[k], ll = p.LL[k];
+#pragma unroll
+        for (int v = 0; v < M; ++v) Qn[v] -= cdt * (lr * Fp[v * NF] - ll * Fm[v * NF]);
+      });
+      const auto pc = PDE::template cell<double>(p.par + cell * K::NPAR);
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        lmax = fmax(lmax, PDE::template speed<I>(Qn, p.g, pc));
+      });
+      if (!PDE::admissible(Qn, p.g, pc)) {
+        bool fin = true;
+#pragma unroll
+        for (int v = 0; v < M; ++v) fin = fin && isfinite(Qn[v]);
+        bad |= fin ? 2 : 1;
+      }
+      double* Qo = p.Qout + (cell * NS + a) * M;
+#pragma unroll
+      for (int v = 0; v < M; ++v) Qo[v] = Qn[v];
+    }
+  }
+  const double bm = block_max<TH>(lmax, red);
+  if (threadIdx.x == 0) p.partial[blockIdx.x] = bm;
+  if (bad && p.flag) atomicOr(p.flag, bad);
+}
+
 // Shifted and fused step (Sec. 5, Techniques 3 and 4; Alg. 2): per cell the
 // corrector of step n (dt of c) and at once the predictor of step n+1 on the
 // new state (dt of p), so Q is read and written once per step.  Cells follow
@@ -1181,6 +1368,7 @@ CorrP<K> corr_params(const LaunchArgs& a) {
     p.w[k] = a.tab->w[k];
   }
   for (int k = 0; k < 3; ++k) p.brick[k] = a.brick[k];
+  p.stf = a.st_face;
   return p;
 }
 
@@ -1202,6 +1390,21 @@ int64_t reduce_grid(int64_t groups) {
 template <class K>
 int launch_correct(const LaunchArgs& a) {
   const CorrP<K> p = corr_params<K>(a);
+  if constexpr (K::ST) {
+    if (a.st_face) {
+      const int64_t gf = (a.ncells + StFace<K>::FCPB - 1) / StFace<K>::FCPB;
+      hipLaunchKernelGGL(k_st_face<K>, dim3((unsigned)(8 * ((gf + 7) / 8))), dim3(StFace<K>::THREADS), 0,
+                         a.stream, p);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return (int)e;
+      const int64_t gu = (a.ncells + StFace<K>::UCPB - 1) / StFace<K>::UCPB;
+      const int64_t G = 8 * ((gu + 7) / 8);
+      if (G > a.n_partial) return (int)hipErrorInvalidValue;
+      *a.n_partial_used = G;
+      hipLaunchKernelGGL(k_st_update<K>, dim3((unsigned)G), dim3(StFace<K>::UTHREADS), 0, a.stream, p);
+      return (int)hipGetLastError();
+    }
+  }
   const int64_t groups = (a.ncells + K::CCPB - 1) / K::CCPB;
   const int64_t G = 8 * ((groups + 7) / 8);
   if (G > a.n_partial) return (int)hipErrorInvalidValue;
@@ -1260,6 +1463,7 @@ Launchers make_fwd_launchers() {
   L.trace_bytes_per_cell = K::TRACE_ELEMS * (int64_t)sizeof(typename K::Real);
   L.qdofs_per_cell = (int64_t)K::NS * K::M;
   L.adj_pf_per_cell = (int64_t)2 * K::D * K::NPAR;
+  L.st_face_per_cell = K::ST ? (int64_t)K::D * K::NF * K::M : 0;
   return L;
 }
 

@@ -170,8 +170,8 @@ def test_query_fused_workspace(L, name):
 
 def test_query_spacetime_traces(L):
     """Space-time traces keep N+1 time values per face node (Table 1's
-    extrapolate output, 4 d m (N+1)^d per cell for Euler); float64 and orders
-    up to 5 only."""
+    extrapolate output, 4 d m (N+1)^d per cell for Euler) and the corrector's
+    time-integrated F* of the d lower faces; float64 and orders up to 5 only."""
     wl = inputs.preset("C2")
     _, _, w = _lib.query(cfg_of(wl))
     c = cfg_of(wl)
@@ -180,7 +180,9 @@ def test_query_spacetime_traces(L):
     n, d, m = wl.n, wl.dim, wl.m
     hull = wl.ncells * 4 * d * m * n ** (d - 1) * 8
     assert wl.ncells * 4 * d * m * n ** d * 8 == n * hull
-    assert abs((ws - w) - (n - 1) * hull) <= 2 * 256
+    # plus the corrector's first pass: F* of each cell's d lower faces
+    fstar = wl.ncells * d * m * n ** (d - 1) * 8
+    assert abs((ws - w) - (n - 1) * hull - fstar) <= 2 * 256
     c.precision = inputs.FP32
     assert L.adg_query(ctypes.byref(c), None, None, None) == _lib.ADG_ERR_UNSUPPORTED
     c = cfg_of(inputs.preset("C5"))
