@@ -124,9 +124,21 @@ struct Fwd {
   // slices in LDS; see pred_cell).  Not for the matrix-core form, whose
   // rounding of the Picard contractions' inputs is part of its definition.
   static constexpr bool CK = PDE::LINEAR && !ST_ && !MX_;
-  static constexpr int CELL_BYTES =
-      ((CK ? (FIRST_BYTES > FIN_BYTES ? FIRST_BYTES : FIN_BYTES)
-           : max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES)) + 15) / 16 * 16;
+  // Long float64 time columns (n >= 7, no slice buffer that holds them all):
+  // each Picard iteration gathers sum_i D_i F_i slice by slice at the node
+  // threads instead of the pencil tasks (see pred_cell).
+  static constexpr bool GATHER = !CK && !MX_ && DBL && !ALIAS && n >= 7;
+  // gather form: flux planes of two slices, used in turn
+  static constexpr int MAIN_BYTES =
+      GATHER ? (2 * FIRST_BYTES > FIN_BYTES ? 2 * FIRST_BYTES : FIN_BYTES)
+      : CK ? (FIRST_BYTES > FIN_BYTES ? FIRST_BYTES : FIN_BYTES) : max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES);
+  // n >= 7: the gathers read D from LDS.  Indexing the kernel argument's
+  // table by a lane-dependent row makes the compiler copy the whole
+  // argument block to scratch memory at that size, and every table read
+  // (also the uniform ones) then goes through scratch.
+  static constexpr bool DLDS = n >= 7 && !MX_;
+  static constexpr int DTAB_OFF = (MAIN_BYTES + 15) / 16 * 16;
+  static constexpr int CELL_BYTES = (DTAB_OFF + (DLDS ? n * n * 8 : 0) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
   // per cell; layout [face][time][qty][var][face node] (face nodes fastest:
@@ -331,6 +343,16 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   // node thread its own value): the node threads write their d fluxes of x,
   // then gather from the d pencils through their node (one barrier before,
   // one after, which frees Fs).
+  // D in LDS for the gathers (n >= 7)
+  [[maybe_unused]] double* sDg = reinterpret_cast<double*>(base + K::DTAB_OFF);
+  if constexpr (K::DLDS) {
+    // static indices only: a dynamic index into the kernel argument would
+    // make the compiler copy the whole argument block to scratch memory
+    if (a == 0) {
+#pragma unroll
+      for (int i = 0; i < n * n; ++i) sDg[i] = p.t.D[i / n][i % n];
+    }
+  }
   auto gather_L = [&](const Real (&x)[M], Real (&rv)[M]) {
     Real* Fs = reinterpret_cast<Real*>(base);      // [axis][var][node] planes
     constexpr bool REF = !std::is_same<Real, double>::value;
@@ -377,7 +399,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
       } else {
 #pragma unroll
         for (int j = 0; j < n; ++j) {
-          const Real dj = p.t.D[ai][j];
+          const Real dj = K::DLDS ? (Real)sDg[ai * n + j] : p.t.D[ai][j];
 #pragma unroll
           for (int v = 0; v < M; ++v) {
             const Real F = Fs[K::template lidx_e<D>(e0 + j * sI, v)];
@@ -445,6 +467,73 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         vk[v] = rv[v];
         qbar_ck[v] = fma(ck * beta, (double)rv[v], qbar_ck[v]);
       }
+    }
+  } else if constexpr (K::GATHER) {
+    // Every node thread evaluates the d fluxes of its node at one slice and
+    // gathers sum_i D_i F_i at that node from the d pencils through it
+    // (gather_L, D from LDS); P is applied from registers as the slices
+    // arrive.  The pencil form at this size keeps a pencil's n m inputs and
+    // outputs live beside the 2 n m values of the time column and its
+    // accumulator, which overflows the register file, and runs one axis at
+    // a time on n^(d-1) of the n^d threads; the gather uses every node
+    // thread and holds m values per slice, at twice the multiply-adds of the
+    // even/odd pencils.
+    // Two flux-plane buffers used in turn: a thread writes buffer g % 2 for
+    // the g-th gather only after the barrier of gather g - 1, which every
+    // reader of gather g - 2 (the same buffer) has passed, so one barrier
+    // per slice suffices.
+    Real* Fb2 = reinterpret_cast<Real*>(base);
+    int g = 0;
+    auto gather_db = [&](const Real (&x)[M], Real (&rv)[M]) {
+      Real* Fs = Fb2 + (g & 1) * (D * NSP * K::MP);
+      ++g;
+      if (node) {
+        Real w[M];
+        PDE::pub(x, w, p.g);
+        static_for<0, D>([&](auto I_) {
+          constexpr int I = decltype(I_)::value;
+          Real F[M];
+          PDE::template flux_pub<I>(w, F, p.g, cp);
+#pragma unroll
+          for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + K::slot(pa), v)] = F[v];
+        });
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < M; ++v) rv[v] = Real(0);
+      if (node) static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        constexpr int sI = K::sstride(I);
+        const int ai = coord<n, I>(pa);
+        const int e0 = I * NSP + K::slot(pa) - ai * sI;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const Real dj = (Real)sDg[ai * n + j];
+#pragma unroll
+          for (int v = 0; v < M; ++v) rv[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], rv[v]);
+        }
+      });
+    };
+    first_iteration();
+    for (int r = 1; r < p.R; ++r) {
+      Real acc[n][M];
+#pragma unroll
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) acc[t][v] = Real(0);
+      static_for<0, n>([&](auto T_) {
+        constexpr int tt = decltype(T_)::value;
+        Real rv[M];
+        gather_db(q[tt], rv);
+#pragma unroll
+        for (int t = 0; t < n; ++t)
+#pragma unroll
+          for (int v = 0; v < M; ++v) acc[t][v] = fma(p.t.P[t][tt], rv[v], acc[t][v]);
+      });
+#pragma unroll
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) q[t][v] = (Real)u[v] - c * acc[t][v];
     }
   } else if constexpr (K::ALIAS) {
     // One pencil per axis per thread and slice: evaluate F_I along the
