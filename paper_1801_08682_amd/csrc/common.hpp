@@ -145,14 +145,23 @@ __device__ __forceinline__ MxOps<n> make_mx_ops(const Tab& t) {
   const int l = (int)(threadIdx.x & 63);
   const int m = l & 15, g = l >> 4;
   const bool mine = (m >> 2) == g;
+  // Rows are picked by selects over static indices: indexing the table by a
+  // lane-dependent row makes the compiler copy the whole kernel argument
+  // block to scratch memory at larger n.
 #pragma unroll
   for (int h = 0; h < MxOps<n>::NH; ++h) {
     const int row = 4 * h + (m & 3);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const bool on = mine && row < n && r < n;
-      const uint16_t bh = on ? t.Dh[row < n ? row : 0][r < n ? r : 0] : (uint16_t)0;
-      const uint16_t bl = on ? t.Dl[row < n ? row : 0][r < n ? r : 0] : (uint16_t)0;
+      uint16_t bh = 0, bl = 0;
+      if (r < n) {
+#pragma unroll
+        for (int rr = 4 * h; rr < 4 * h + 4 && rr < n; ++rr) {
+          bh = (row == rr) ? t.Dh[rr][r] : bh;
+          bl = (row == rr) ? t.Dl[rr][r] : bl;
+        }
+      }
+      if (!mine) bh = bl = 0;
       o.hi[h][r] = __builtin_bit_cast(__bf16, bh);
       o.lo[h][r] = __builtin_bit_cast(__bf16, bl);
     }

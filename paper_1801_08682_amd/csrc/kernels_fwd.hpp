@@ -136,7 +136,7 @@ struct Fwd {
   // table by a lane-dependent row makes the compiler copy the whole
   // argument block to scratch memory at that size, and every table read
   // (also the uniform ones) then goes through scratch.
-  static constexpr bool DLDS = n >= 7 && !MX_;
+  static constexpr bool DLDS = n >= 7;
   static constexpr int DTAB_OFF = (MAIN_BYTES + 15) / 16 * 16;
   static constexpr int CELL_BYTES = (DTAB_OFF + (DLDS ? n * n * 8 : 0) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
@@ -150,7 +150,7 @@ struct Fwd {
   static constexpr int CT = NS > FT ? NS : FT;
   static constexpr int CCPB = (CT >= 128) ? 1 : 128 / CT;
   static constexpr int CTHREADS = CCPB * CT;
-  static constexpr int CORR_CELL_BYTES = (2 * D * NF * (M + NT) + 2 * D * NT) * 8;
+  static constexpr int CORR_CELL_BYTES = (2 * D * NF * (M + NT) + 2 * D * NT + (n >= 7 ? 2 * n : 0)) * 8;
 };
 
 template <int D_, int N_, template <int> class PDET, class Real_, bool ST_, bool MX_>
@@ -343,14 +343,14 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   // node thread its own value): the node threads write their d fluxes of x,
   // then gather from the d pencils through their node (one barrier before,
   // one after, which frees Fs).
-  // D in LDS for the gathers (n >= 7)
+  // D (the matrix-core form: Dx) in LDS for the gathers (n >= 7)
   [[maybe_unused]] double* sDg = reinterpret_cast<double*>(base + K::DTAB_OFF);
   if constexpr (K::DLDS) {
     // static indices only: a dynamic index into the kernel argument would
     // make the compiler copy the whole argument block to scratch memory
     if (a == 0) {
 #pragma unroll
-      for (int i = 0; i < n * n; ++i) sDg[i] = p.t.D[i / n][i % n];
+      for (int i = 0; i < n * n; ++i) sDg[i] = K::MX ? (double)p.t.Dx[i / n][i % n] : (double)p.t.D[i / n][i % n];
     }
   }
   auto gather_L = [&](const Real (&x)[M], Real (&rv)[M]) {
@@ -393,7 +393,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
 #pragma unroll
           for (int j = 0; j < n; ++j) {
             const float x = (float)(__bf16)(F[j][v] - Fr);
-            rv[v] = fma(p.t.Dx[ai][j], x, rv[v]);
+            rv[v] = fma(K::DLDS ? (float)sDg[ai * n + j] : p.t.Dx[ai][j], x, rv[v]);
           }
         }
       } else {
@@ -889,6 +889,17 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
   double* lam = lds;                                     // [2D][NT][NF]
   double* Fs = lam + 2 * D * NF * K::NT;                 // [2D][NF][M]
   double* sm = Fs + 2 * D * NF * M;                      // [2D][NT]
+  // n >= 7: LL and LR in LDS (see DLDS), read after the face barriers
+  [[maybe_unused]] double* sLf = sm + 2 * D * K::NT;
+  if constexpr (K::DLDS) {
+    if (t == 0) {
+#pragma unroll
+      for (int kk = 0; kk < n; ++kk) {
+        sLf[kk] = p.LL[kk];
+        sLf[n + kk] = p.LR[kk];
+      }
+    }
+  }
   const double cdt = (*p.dt) * p.inv_h;
   if constexpr (K::ST) {
     // Space-time traces: every trace is read once.  The time loop of each
@@ -1084,7 +1095,14 @@ __device__ __forceinline__ void corr_cell(const CorrP<K>& p, double* lds, int t,
       const int b = face_node<n, I>(a);
       const double* Fm = Fs + ((2 * I) * NF + b) * M;
       const double* Fp = Fs + ((2 * I + 1) * NF + b) * M;
-      const double lr = p.LR[k], ll = p.LL[k];
+      double lr, ll;
+      if constexpr (K::DLDS) {
+        lr = sLf[n + k];
+        ll = sLf[k];
+      } else {
+        lr = p.LR[k];
+        ll = p.LL[k];
+      }
 #pragma unroll
       for (int v = 0; v < M; ++v) Qn[v] -= cdt * (lr * Fp[v] - ll * Fm[v]);
     });
