@@ -72,6 +72,10 @@ struct Fwd {
   // gcd(n, 16) lanes of a 16-lane access on one bank (4-way at n = 4, 8-way
   // at n = 8; the 2-way case n = 6 is cheaper than the padding).
   static constexpr int XP = (n % 4 == 0) ? n + 1 : n;
+  // Long float64 time columns (n >= 7, nonlinear flux): each Picard
+  // iteration gathers sum_i D_i F_i slice by slice at the node threads
+  // instead of the pencil tasks (see pred_cell).
+  static constexpr bool GATHER = !(PDE::LINEAR && !ST_ && !MX_) && !MX_ && DBL && n >= 7;
   static constexpr int NSLOT = XP * NF;
   __host__ __device__ static constexpr int slot(int node) { return (node % n) + XP * (node / n); }
   __host__ __device__ static constexpr int sstride(int I) { return I == 0 ? 1 : XP * ipow(n, I - 1); }
@@ -124,10 +128,7 @@ struct Fwd {
   // slices in LDS; see pred_cell).  Not for the matrix-core form, whose
   // rounding of the Picard contractions' inputs is part of its definition.
   static constexpr bool CK = PDE::LINEAR && !ST_ && !MX_;
-  // Long float64 time columns (n >= 7, no slice buffer that holds them all):
-  // each Picard iteration gathers sum_i D_i F_i slice by slice at the node
-  // threads instead of the pencil tasks (see pred_cell).
-  static constexpr bool GATHER = !CK && !MX_ && DBL && !ALIAS && n >= 7;
+  static_assert(!(GATHER && (ALIAS || CK)), "the gather form replaces the batched pencils only");
   // gather form: flux planes of two slices, used in turn
   static constexpr int MAIN_BYTES =
       GATHER ? (2 * FIRST_BYTES > FIN_BYTES ? 2 * FIRST_BYTES : FIN_BYTES)
@@ -138,7 +139,8 @@ struct Fwd {
   // (also the uniform ones) then goes through scratch.
   static constexpr bool DLDS = n >= 7;
   static constexpr int DTAB_OFF = (MAIN_BYTES + 15) / 16 * 16;
-  static constexpr int CELL_BYTES = (DTAB_OFF + (DLDS ? n * n * 8 : 0) + 15) / 16 * 16;
+  static constexpr int DROW = n + 1;                 // D rows padded: 8 rows n apart share banks
+  static constexpr int CELL_BYTES = (DTAB_OFF + (DLDS ? n * DROW * 8 : 0) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
   // per cell; layout [face][time][qty][var][face node] (face nodes fastest:
@@ -350,7 +352,8 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     // make the compiler copy the whole argument block to scratch memory
     if (a == 0) {
 #pragma unroll
-      for (int i = 0; i < n * n; ++i) sDg[i] = K::MX ? (double)p.t.Dx[i / n][i % n] : (double)p.t.D[i / n][i % n];
+      for (int i = 0; i < n * n; ++i)
+        sDg[(i / n) * K::DROW + i % n] = K::MX ? (double)p.t.Dx[i / n][i % n] : (double)p.t.D[i / n][i % n];
     }
   }
   auto gather_L = [&](const Real (&x)[M], Real (&rv)[M]) {
@@ -393,13 +396,13 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
 #pragma unroll
           for (int j = 0; j < n; ++j) {
             const float x = (float)(__bf16)(F[j][v] - Fr);
-            rv[v] = fma(K::DLDS ? (float)sDg[ai * n + j] : p.t.Dx[ai][j], x, rv[v]);
+            rv[v] = fma(K::DLDS ? (float)sDg[ai * K::DROW + j] : p.t.Dx[ai][j], x, rv[v]);
           }
         }
       } else {
 #pragma unroll
         for (int j = 0; j < n; ++j) {
-          const Real dj = K::DLDS ? (Real)sDg[ai * n + j] : p.t.D[ai][j];
+          const Real dj = K::DLDS ? (Real)sDg[ai * K::DROW + j] : p.t.D[ai][j];
 #pragma unroll
           for (int v = 0; v < M; ++v) {
             const Real F = Fs[K::template lidx_e<D>(e0 + j * sI, v)];
@@ -508,7 +511,7 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
         const int e0 = I * NSP + K::slot(pa) - ai * sI;
 #pragma unroll
         for (int j = 0; j < n; ++j) {
-          const Real dj = (Real)sDg[ai * n + j];
+          const Real dj = (Real)sDg[ai * K::DROW + j];
 #pragma unroll
           for (int v = 0; v < M; ++v) rv[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], rv[v]);
         }
