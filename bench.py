@@ -190,6 +190,65 @@ def adjoint_bench(args):
             "grad_norm_p0": float(Qg.grad[..., 0].norm()), "grad_norm_c": float(cg.grad.norm())}
 
 
+def c5_gradient_bench(args):
+    """C5 at full size: 3D Euler N=7, 48^3 cells, Fourier density, 50 steps
+    with the device-computed dt (recorded, then held fixed in the reverse
+    sweep), gradient of the final kinetic energy w.r.t. the initial density
+    DoFs by the checkpointed rollout (checkpoint every 10).  float64 forward
+    and adjoint; also one adg_step_adjoint against one adg_step."""
+    import numpy as np
+    import torch
+    from paper_1801_08682_amd import inputs
+    from paper_1801_08682_amd.rollout import kinetic_energy, rollout
+    from paper_1801_08682_amd.stepper import Stepper
+    wl = inputs.preset("C5")
+    steps, k = args.adj_steps if args.adj_steps != 200 else wl.steps, wl.extra["checkpoint"]
+    Q0 = torch.tensor(inputs.initial_state(wl, seed=0), device="cuda")
+    z, om = np.polynomial.legendre.leggauss(wl.n)
+    w1 = torch.tensor(0.5 * om, device="cuda")
+    st = Stepper(wl, adjoint=True)
+    # untimed warm-up of the backward path over one checkpoint interval
+    Qw = Q0.clone().requires_grad_(True)
+    QN, _ = rollout(st, Qw, None, k, cfl=wl.cfl, checkpoint_every=k)
+    kinetic_energy(QN, 3, wl.h, w1).backward()
+    del Qw, QN
+    Q = Q0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.run(Q, None, steps, cfl=wl.cfl)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    Qg = Q0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    QN, _ = rollout(st, Qg, None, steps, cfl=wl.cfl, checkpoint_every=k)
+    KE = kinetic_energy(QN, 3, wl.h, w1)
+    KE.backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    g = Qg.grad[..., 0]
+    Qs, Gs = Q0.clone(), torch.randn_like(Q0)
+    dts = st.scalar(wl.cfl * wl.h / (3 * (2 * wl.order + 1) * 2.0))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    st.step_adjoint(Qs, None, dts, Gs, None)
+    torch.cuda.synchronize()
+    reps = 5
+    ev[0].record()
+    for _ in range(reps):
+        st.step(Qs, None, dts)
+    ev[1].record()
+    for _ in range(reps):
+        st.step_adjoint(Qs, None, dts, Gs, None)
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd_ms, adj_ms = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+    st.close()
+    return {"workload": f"3D Euler N=7, 48^3 cells, {steps} steps, final kinetic energy, "
+                        f"checkpoint every {k}", "forward_s": t_fwd, "forward_plus_backward_s": t_fb,
+            "ratio": t_fb / t_fwd, "KE": float(KE.detach()), "grad_norm_rho0": float(g.norm()),
+            "step_ms": fwd_ms, "adjoint_step_ms": adj_ms, "step_ratio": adj_ms / fwd_ms}
+
+
 def other_workload(args, torch):
     """One line for a non-headline workload: float64 and float-predictor
     throughput over its step count and the float path's per-field L2
@@ -355,6 +414,8 @@ def main():
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="print only the C4 adjoint rollout's line")
+    ap.add_argument("--c5-gradient", action="store_true",
+                    help="print only the C5 kinetic-energy gradient rollout's line")
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"],
                     help="C2 is the headline line; the others print their own line "
@@ -381,6 +442,9 @@ def main():
     from paper_1801_08682_amd import inputs
     from paper_1801_08682_amd.stepper import Stepper
 
+    if args.c5_gradient:
+        print(json.dumps(c5_gradient_bench(args)), flush=True)
+        return
     if args.adjoint_only:
         res = adjoint_bench(args)
         if args.copy_calib_mb:

@@ -533,6 +533,265 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
   }
 }
 
+// Long float64 time columns (the forward predictor's gather form, n >= 7,
+// nonlinear flux): the same reverse sweep as k_adj_pred with every spatial
+// contraction done by gathers at the node threads instead of pencil tasks,
+// slice by slice, with two LDS buffers in turn (one barrier per slice):
+//  1. recompute q^1..q^R (q^1..q^{R-1} to the block's slot, q^R kept);
+//  2. bars of qbar and Fbar_i from the trace bars and Kv^T G (tables in LDS);
+//  3. for r = R..2: u bar += sum_t q^r bar; per slice l: rhs bar_l =
+//     -(dt/h) sum_t P[t][l] q^r bar_t is published, each node gathers
+//     F_i bar = D_i^T rhs bar_l along its d pencils and adds
+//     J_i(q^{r-1}_l)^T F_i bar to q^{r-1} bar_l;
+//  4. r = 1 on one slice with the row sums of P, Jacobians at u.
+template <class K>
+struct AdjGather {
+  static constexpr int PL = K::D * K::NSP * K::MP;           // doubles of one flux-plane set
+  static constexpr int DR = K::n + 1;                        // padded table rows
+  static constexpr int TAB = 2 * K::n * DR + 2 * K::n;       // D, Kv, FL, FR
+  static constexpr int CELL = 2 * PL + TAB;
+};
+
+template <class K>
+__global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K> p) {
+  using PDE = typename K::PDE;
+  using Gp = AdjGather<K>;
+  constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, NPAR = K::NPAR;
+  constexpr int NSP = K::NSP, PL = Gp::PL, DR = Gp::DR;
+  static_assert(K::CPB == 1, "one cell per workgroup");
+  static_assert(NPAR * NS <= 2 * PL, "material bars reuse the flux planes");
+  __shared__ __align__(16) double smem[Gp::CELL];
+  double* Fp = smem;                                   // two flux-plane sets
+  double* sD = smem + 2 * PL;                          // D[k][j] at k * DR + j
+  double* sKv = sD + n * DR;
+  double* sFL = sKv + n * DR;
+  double* sFR = sFL + n;
+  const int a = threadIdx.x;
+  // tables by static indices (a lane-dependent index into the kernel
+  // argument would copy the whole argument block to scratch memory)
+  if (a == 0) {
+#pragma unroll
+    for (int i = 0; i < n * n; ++i) {
+      sD[(i / n) * DR + i % n] = p.t.D[i / n][i % n];
+      sKv[(i / n) * DR + i % n] = p.t.Kv[i / n][i % n];
+    }
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      sFL[i] = p.t.FL[i];
+      sFR[i] = p.t.FR[i];
+    }
+  }
+  double* slot = p.scratch + (int64_t)blockIdx.x * p.slot_doubles;
+  const int64_t LV = (int64_t)n * M * NS;
+  auto it_at = [&](int r, int t, int v) -> double& { return slot[(r - 1) * LV + (int64_t)(t * M + v) * NS + a]; };
+  const double c = (*p.dt) * p.inv_h;
+  int g = 0;                                           // gathers so far: buffer g % 2
+
+  for (int64_t cell = blockIdx.x; cell < p.ncells; cell += gridDim.x) {
+    double u[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) u[v] = p.Q[(cell * NS + a) * M + v];
+    const auto cp = PDE::template cell<double>(p.par + cell * NPAR);
+    double pb[NPAR > 0 ? NPAR : 1];
+#pragma unroll
+    for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
+
+    // rv = sum_i D_i F_i(x) at this node (forward gather)
+    auto gather_f = [&](const double (&x)[M], double (&rv)[M]) {
+      double* Fs = Fp + (g & 1) * PL;
+      ++g;
+      double w[M];
+      PDE::pub(x, w, p.g);
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        double F[M];
+        PDE::template flux_pub<I>(w, F, p.g, cp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + K::slot(a), v)] = F[v];
+      });
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < M; ++v) rv[v] = 0.0;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        constexpr int sI = K::sstride(I);
+        const int ai = coord<n, I>(a);
+        const int e0 = I * NSP + K::slot(a) - ai * sI;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const double dj = sD[ai * DR + j];
+#pragma unroll
+          for (int v = 0; v < M; ++v) rv[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], rv[v]);
+        }
+      });
+    };
+    // out += sum_i J_i(z)^T (D_i^T y) at this node (reverse gather of y)
+    auto gather_r = [&](const double (&y)[M], const double (&z)[M], double (&out)[M]) {
+      double* Fs = Fp + (g & 1) * PL;
+      ++g;
+#pragma unroll
+      for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(K::slot(a), v)] = y[v];
+      __syncthreads();
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        constexpr int sI = K::sstride(I);
+        const int ai = coord<n, I>(a);
+        const int e0 = K::slot(a) - ai * sI;
+        double fb[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) fb[v] = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const double dk = sD[k * DR + ai];
+#pragma unroll
+          for (int v = 0; v < M; ++v) fb[v] = fma(dk, Fs[K::template lidx_e<D>(e0 + k * sI, v)], fb[v]);
+        }
+        PDE::template flux_adj<I>(z, fb, out, pb, p.g, cp);
+      });
+    };
+
+    // ---- 1. recompute the Picard iterates ----
+    double q[n][M];
+    {
+      double rv[M];
+      gather_f(u, rv);
+#pragma unroll
+      for (int v = 0; v < M; ++v)
+#pragma unroll
+        for (int t = 0; t < n; ++t) q[t][v] = u[v] - c * (p.t.Ps[t] * rv[v]);
+    }
+    for (int r = 2; r <= p.R; ++r) {
+      double acc[n][M];
+#pragma unroll
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          it_at(r - 1, t, v) = q[t][v];
+          acc[t][v] = 0.0;
+        }
+      static_for<0, n>([&](auto T_) {
+        constexpr int tt = decltype(T_)::value;
+        double rv[M];
+        gather_f(q[tt], rv);
+#pragma unroll
+        for (int t = 0; t < n; ++t)
+#pragma unroll
+          for (int v = 0; v < M; ++v) acc[t][v] = fma(p.t.P[t][tt], rv[v], acc[t][v]);
+      });
+#pragma unroll
+      for (int t = 0; t < n; ++t)
+#pragma unroll
+        for (int v = 0; v < M; ++v) q[t][v] = u[v] - c * acc[t][v];
+    }
+
+    // ---- 2. bars of qbar and Fbar_i at this node, then q^R bar ----
+    const double* TB = p.tb + cell * K::TRACE_ELEMS;
+    const double* Gc = p.Qbar + cell * NS * M;
+    double qb[n][M];
+    {
+      double qbb[M], Fbb[D][M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) qbb[v] = 0.0;
+      static_for<0, D>([&](auto I_) {
+        constexpr int I = decltype(I_)::value;
+        const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
+        const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb;
+        const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb;
+        const double fl = sFL[ai], fr = sFR[ai];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          qbb[v] += fl * tl[v * NF] + fr * trr[v * NF];
+          Fbb[I][v] = (K::NQ == 2) ? fl * tl[NF * M + v * NF] + fr * trr[NF * M + v * NF] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const int nd = pencil_node<n, I>(fb, k);
+          const double kv = c * sKv[k * DR + ai];
+#pragma unroll
+          for (int v = 0; v < M; ++v) Fbb[I][v] += kv * Gc[nd * M + v];
+        }
+      });
+#pragma unroll
+      for (int t = 0; t < n; ++t) {
+        const double wt = p.t.w[t];
+#pragma unroll
+        for (int v = 0; v < M; ++v) qb[t][v] = wt * qbb[v];
+        static_for<0, D>([&](auto I_) {
+          constexpr int I = decltype(I_)::value;
+          double fw[M];
+#pragma unroll
+          for (int v = 0; v < M; ++v) fw[v] = wt * Fbb[I][v];
+          PDE::template flux_adj<I>(q[t], fw, qb[t], pb, p.g, cp);
+        });
+      }
+    }
+    double ub[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) ub[v] = Gc[a * M + v];
+
+    // ---- 3. reverse sweep over the Picard iterations ----
+    // (all rhs bars first: then the q^r bars are dead, and the rhs bars of
+    // the slices still to come and the q^{r-1} bars of the slices done
+    // together hold n m values)
+    for (int r = p.R; r >= 2; --r) {
+      double rb[n][M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+#pragma unroll
+        for (int t = 0; t < n; ++t) ub[v] += qb[t][v];
+#pragma unroll
+        for (int l = 0; l < n; ++l) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < n; ++t) s = fma(p.t.P[t][l], qb[t][v], s);
+          rb[l][v] = -c * s;
+        }
+      }
+      static_for<0, n>([&](auto L_) {
+        constexpr int l = decltype(L_)::value;
+        double z[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          z[v] = it_at(r - 1, l, v);
+          qb[l][v] = 0.0;
+        }
+        gather_r(rb[l], z, qb[l]);
+      });
+    }
+    // r = 1: q^1 = u - (dt/h) Ps rhs(u), one slice
+    {
+      double rb0[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < n; ++t) {
+          ub[v] += qb[t][v];
+          s = fma(p.t.Ps[t], qb[t][v], s);
+        }
+        rb0[v] = -c * s;
+      }
+      gather_r(rb0, u, ub);
+    }
+    __syncthreads();                       // every read of this cell's G and LDS is done
+#pragma unroll
+    for (int v = 0; v < M; ++v) p.Qbar[(cell * NS + a) * M + v] = ub[v];
+    if constexpr (NPAR > 0) {
+      double* pred = smem;
+#pragma unroll
+      for (int k = 0; k < NPAR; ++k) pred[k * NS + a] = pb[k];
+      __syncthreads();
+      if (a < NPAR && p.pbar) {
+        double acc = 0.0;
+        for (int j = 0; j < NS; ++j) acc += pred[a * NS + j];
+        for (int f = 0; f < 2 * D; ++f) acc += p.pf[(cell * 2 * D + f) * NPAR + a];
+        p.pbar[cell * NPAR + a] += acc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Linear fluxes (the power form of the forward predictor, see pred_cell): the
 // time average is qbar = z_0 of the Horner recursion z_R = a_R u,
 // z_k = a_k u + L z_{k+1}, a_k = (-dt/h)^k w.T_k (T_0 = 1, T_k = P^{k-1} Ps),
@@ -813,6 +1072,24 @@ int launch_adjoint(const LaunchArgs& a) {
       hipLaunchKernelGGL(k_adj_pred_ck<K>, dim3((unsigned)G), dim3(K::NODE_THREADS), 0, a.stream, pp);
       return (int)hipGetLastError();
     }
+  }
+  if constexpr (K::GATHER) {
+    // long float64 columns: the gather form (one cell per workgroup)
+    static int resident_g = 0;
+    if (resident_g == 0) {
+      int dev = 0, cus = 0, per_cu = 0;
+      e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_pred_g<K>, K::NODE_THREADS, 0);
+      if (e != hipSuccess) return (int)e;
+      resident_g = cus * (per_cu > 0 ? per_cu : 1);
+    }
+    int64_t G = a.ncells;
+    if (G > a.adj_nslots) G = a.adj_nslots;
+    if (G > resident_g) G = resident_g;
+    hipLaunchKernelGGL(k_adj_pred_g<K>, dim3((unsigned)G), dim3(K::NODE_THREADS), 0, a.stream, pp);
+    return (int)hipGetLastError();
   }
   // Persistent blocks: no more than fit on the device at once, so every
   // block starts together and walks the same number of cells.
