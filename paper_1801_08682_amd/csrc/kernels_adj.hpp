@@ -544,6 +544,8 @@ __global__ void __launch_bounds__(K::THREADS) k_adj_pred(const AdjPredP<K> p) {
 //     F_i bar = D_i^T rhs bar_l along its d pencils and adds
 //     J_i(q^{r-1}_l)^T F_i bar to q^{r-1} bar_l;
 //  4. r = 1 on one slice with the row sums of P, Jacobians at u.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 template <class K>
 struct AdjGather {
   static constexpr int PL = K::D * K::NSP * K::MP;           // doubles of one flux-plane set
@@ -581,9 +583,22 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
       sFR[i] = p.t.FR[i];
     }
   }
+  // The block's slot of stored iterates through buffer instructions: a
+  // scalar resource and offset per (r, t, v) and one lane offset register,
+  // where 64-bit lane addresses would hold a register pair per access.
   double* slot = p.scratch + (int64_t)blockIdx.x * p.slot_doubles;
-  const int64_t LV = (int64_t)n * M * NS;
-  auto it_at = [&](int r, int t, int v) -> double& { return slot[(r - 1) * LV + (int64_t)(t * M + v) * NS + a]; };
+  const __amdgpu_buffer_rsrc_t srs =
+      __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, (int)(p.slot_doubles * 8), 0x00020000);
+  const int LVB = n * M * NS * 8;                      // bytes of one iterate
+  const int lane_off = a * 8;
+  auto it_st = [&](int r, int t, int v, double x) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), srs, lane_off,
+                                          (r - 1) * LVB + (t * M + v) * NS * 8, 0);
+  };
+  auto it_ld = [&](int r, int t, int v) -> double {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(srs, lane_off,
+                                                                           (r - 1) * LVB + (t * M + v) * NS * 8, 0));
+  };
   const double c = (*p.dt) * p.inv_h;
   int g = 0;                                           // gathers so far: buffer g % 2
 
@@ -666,7 +681,7 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
       for (int t = 0; t < n; ++t)
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          it_at(r - 1, t, v) = q[t][v];
+          it_st(r - 1, t, v, q[t][v]);
           acc[t][v] = 0.0;
         }
       static_for<0, n>([&](auto T_) {
@@ -694,6 +709,7 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
       for (int v = 0; v < M; ++v) qbb[v] = 0.0;
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
+        __builtin_amdgcn_sched_barrier(0);               // one axis's loads in flight
         const int ai = coord<n, I>(a), fb = face_node<n, I>(a);
         const double* tl = TB + (int64_t)(2 * I) * K::NQ * NF * M + fb;
         const double* trr = TB + (int64_t)(2 * I + 1) * K::NQ * NF * M + fb;
@@ -713,6 +729,7 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
       });
 #pragma unroll
       for (int t = 0; t < n; ++t) {
+        __builtin_amdgcn_sched_barrier(0);               // slices one at a time
         const double wt = p.t.w[t];
 #pragma unroll
         for (int v = 0; v < M; ++v) qb[t][v] = wt * qbb[v];
@@ -752,7 +769,7 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
         double z[M];
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          z[v] = it_at(r - 1, l, v);
+          z[v] = it_ld(r - 1, l, v);
           qb[l][v] = 0.0;
         }
         gather_r(rb[l], z, qb[l]);
