@@ -586,7 +586,8 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     Real out[D][n][M];
     first_iteration();
     for (int r = 1; r < p.R; ++r) {
-      if (r > 1) __syncthreads();                   // every node has read the last rhs
+      // no barrier before the publish: a node thread reads its own slots'
+      // rhs below and overwrites only those same slots here
       publish(std::integral_constant<int, 0>{}, std::integral_constant<int, n>{});
       __syncthreads();
       pencils(std::integral_constant<int, n>{}, out);
