@@ -813,9 +813,10 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
 // time average is qbar = z_0 of the Horner recursion z_R = a_R u,
 // z_k = a_k u + L z_{k+1}, a_k = (-dt/h)^k w.T_k (T_0 = 1, T_k = P^{k-1} Ps),
 // L = sum_i D_i F_i.  Per cell:
-//  1. forward Horner: R gathers of L; z_1..z_R go to the block's scratch slot
-//     when material bars are wanted (they are the states of the bilinear
-//     material terms; the Jacobians themselves do not depend on the state);
+//  1. forward Horner: R gathers of L; z_1..z_R are kept when material bars
+//     are wanted (they are the states of the bilinear material terms; the
+//     Jacobians themselves do not depend on the state), in LDS beside the
+//     gather planes when they fit, else in the block's scratch slot;
 //  2. bars of qbar and Fbar_i = F_i(qbar) from the trace bars and Kv^T G, as
 //     in k_adj_pred; zbar_0 = qbar bar + sum_i J_i^T Fbar_i bar;
 //  3. reverse Horner: u bar += a_k zbar_k, zbar_{k+1} = L^T zbar_k,
@@ -824,6 +825,8 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
 // node.  No Picard iterates and no time slices: 2R gathers of one field
 // against R sweeps over n slices.  Used for R = N + 1 (the default).
 template <class K>
+// (At least two waves per SIMD: the large-m instantiations then spill a
+// few registers instead of running one wave per SIMD.)
 __global__ void __launch_bounds__(K::NODE_THREADS) __attribute__((amdgpu_waves_per_eu(2))) k_adj_pred_ck(const AdjPredP<K> p) {
   using PDE = typename K::PDE;
   constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, NPAR = K::NPAR;
