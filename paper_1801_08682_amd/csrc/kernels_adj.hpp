@@ -550,7 +550,7 @@ template <class K>
 struct AdjGather {
   static constexpr int PL = K::D * K::NSP * K::MP;           // doubles of one flux-plane set
   static constexpr int DR = K::n + 1;                        // padded table rows
-  static constexpr int TAB = 2 * K::n * DR + 2 * K::n;       // D, Kv, FL, FR
+  static constexpr int TAB = 3 * K::n * DR + 2 * K::n;       // D, Kv, P, FL, FR
   static constexpr int CELL = 2 * PL + TAB;
 };
 
@@ -566,16 +566,19 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
   double* Fp = smem;                                   // two flux-plane sets
   double* sD = smem + 2 * PL;                          // D[k][j] at k * DR + j
   double* sKv = sD + n * DR;
-  double* sFL = sKv + n * DR;
+  double* sP = sKv + n * DR;                           // P[t][l] at t * DR + l
+  double* sFL = sP + n * DR;
   double* sFR = sFL + n;
   const int a = threadIdx.x;
   // tables by static indices (a lane-dependent index into the kernel
-  // argument would copy the whole argument block to scratch memory)
+  // argument would copy the whole argument block to scratch memory); P too:
+  // read in the loops from LDS, its n^2 values are not held in registers
   if (a == 0) {
 #pragma unroll
     for (int i = 0; i < n * n; ++i) {
       sD[(i / n) * DR + i % n] = p.t.D[i / n][i % n];
       sKv[(i / n) * DR + i % n] = p.t.Kv[i / n][i % n];
+      sP[(i / n) * DR + i % n] = p.t.P[i / n][i % n];
     }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
@@ -691,7 +694,7 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
 #pragma unroll
         for (int t = 0; t < n; ++t)
 #pragma unroll
-          for (int v = 0; v < M; ++v) acc[t][v] = fma(p.t.P[t][tt], rv[v], acc[t][v]);
+          for (int v = 0; v < M; ++v) acc[t][v] = fma(sP[t * DR + tt], rv[v], acc[t][v]);
       });
 #pragma unroll
       for (int t = 0; t < n; ++t)
@@ -760,19 +763,26 @@ __global__ void __launch_bounds__(K::NODE_THREADS) k_adj_pred_g(const AdjPredP<K
         for (int l = 0; l < n; ++l) {
           double s = 0.0;
 #pragma unroll
-          for (int t = 0; t < n; ++t) s = fma(p.t.P[t][l], qb[t][v], s);
+          for (int t = 0; t < n; ++t) s = fma(sP[t * DR + l], qb[t][v], s);
           rb[l][v] = -c * s;
         }
       }
+      // the stored iterate of slice l + 1 is loaded before the barrier of
+      // slice l, so its latency overlaps that slice's gather
+      double zc[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) zc[v] = it_ld(r - 1, 0, v);
       static_for<0, n>([&](auto L_) {
         constexpr int l = decltype(L_)::value;
-        double z[M];
+        double zn[M];
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-          z[v] = it_ld(r - 1, l, v);
+          zn[v] = (l + 1 < n) ? it_ld(r - 1, l + 1 < n ? l + 1 : l, v) : 0.0;
           qb[l][v] = 0.0;
         }
-        gather_r(rb[l], z, qb[l]);
+        gather_r(rb[l], zc, qb[l]);
+#pragma unroll
+        for (int v = 0; v < M; ++v) zc[v] = zn[v];
       });
     }
     // r = 1: q^1 = u - (dt/h) Ps rhs(u), one slice
