@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cmath>
 #include <cstring>
 #include <type_traits>
 
@@ -64,6 +65,12 @@ struct KTab {
   // sum is a 16-bit-significand operator that float32 holds exactly.
   uint16_t Dh[n][n], Dl[n][n];
   float Dx[n][n];   // Dh + Dl as a float (exact)
+  // Power form of the linear predictor: beta[k-1] = w . P^(k-1) Ps for
+  // k = 1..BK, from the (Real-rounded) P and Ps as the device used to
+  // recompute them.  L^k u vanishes for k > d N (a degree-N polynomial per
+  // axis, piecewise-constant material), so BK = 3 n + 3 terms cover every R.
+  static constexpr int BK = 3 * n + 3;
+  double beta[BK];
 };
 
 // float -> bfloat16 bit pattern, round to nearest, ties to even (finite x).
@@ -113,6 +120,23 @@ inline KTab<n, Real> make_ktab(const HostTables& h) {
       t.Dl[k][j] = bf16_bits_rne((float)(d - bf16_bits_value(t.Dh[k][j])));
       t.Dx[k][j] = (float)(bf16_bits_value(t.Dh[k][j]) + bf16_bits_value(t.Dl[k][j]));
     }
+  {
+    double T[n], Tn[n];
+    for (int a = 0; a < n; ++a) T[a] = (double)t.Ps[a];
+    for (int k = 1; k <= KTab<n, Real>::BK; ++k) {
+      if (k > 1) {
+        for (int a = 0; a < n; ++a) {
+          double s = 0.0;
+          for (int j = 0; j < n; ++j) s = std::fma((double)t.P[a][j], T[j], s);
+          Tn[a] = s;
+        }
+        for (int a = 0; a < n; ++a) T[a] = Tn[a];
+      }
+      double b = 0.0;
+      for (int a = 0; a < n; ++a) b = std::fma(t.w[a], T[a], b);
+      t.beta[k - 1] = b;
+    }
+  }
   return t;
 }
 

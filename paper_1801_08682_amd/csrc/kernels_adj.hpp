@@ -857,24 +857,13 @@ __global__ void __launch_bounds__(K::NODE_THREADS) __attribute__((amdgpu_waves_p
   const double c = (*p.dt) * p.inv_h;
   for (int i = threadIdx.x; i < n * n; i += K::NODE_THREADS) s_D[i / n][i % n] = p.t.D[i / n][i % n];
   if (threadIdx.x == 0) {
-    // a_k for k = 0..R (R = N + 1), uniform over the grid
-    double T[n], ck = 1.0;
-    for (int t = 0; t < n; ++t) T[t] = p.t.Ps[t];
+    // a_k = (-dt/h)^k w.T_k for k = 0..R (R = N + 1), the forward's table
+    double ck = 1.0;
     s_al[0] = 1.0;
+#pragma unroll
     for (int k = 1; k <= RR; ++k) {
-      if (k > 1) {
-        double Tn[n];
-        for (int t = 0; t < n; ++t) {
-          double s = 0.0;
-          for (int tt = 0; tt < n; ++tt) s = fma(p.t.P[t][tt], T[tt], s);
-          Tn[t] = s;
-        }
-        for (int t = 0; t < n; ++t) T[t] = Tn[t];
-      }
       ck *= -c;
-      double beta = 0.0;
-      for (int t = 0; t < n; ++t) beta = fma(p.t.w[t], T[t], beta);
-      s_al[k] = ck * beta;
+      s_al[k] = ck * p.t.beta[k - 1];
     }
   }
   __syncthreads();

@@ -130,9 +130,12 @@ struct Fwd {
   static constexpr bool CK = PDE::LINEAR && !ST_ && !MX_;
   static_assert(!(GATHER && (ALIAS || CK)), "the gather form replaces the batched pencils only");
   // gather form: flux planes of two slices, used in turn
+  // linear flux: the finalisation takes Fbar_i = F_i(qbar) one axis at a
+  // time (qbar, V and one flux plane)
+  static constexpr int FIN_CK_BYTES = 3 * NS * M * 8;
   static constexpr int MAIN_BYTES =
       GATHER ? (2 * FIRST_BYTES > FIN_BYTES ? 2 * FIRST_BYTES : FIN_BYTES)
-      : CK ? (FIRST_BYTES > FIN_BYTES ? FIRST_BYTES : FIN_BYTES) : max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES);
+      : CK ? (FIRST_BYTES > FIN_CK_BYTES ? FIRST_BYTES : FIN_CK_BYTES) : max3(PIC_BYTES, FIRST_BYTES, FIN_BYTES);
   // n >= 7: the gathers read D from LDS.  Indexing the kernel argument's
   // table by a lane-dependent row makes the compiler copy the whole
   // argument block to scratch memory at that size, and every table read
@@ -140,7 +143,9 @@ struct Fwd {
   static constexpr bool DLDS = n >= 7;
   static constexpr int DTAB_OFF = (MAIN_BYTES + 15) / 16 * 16;
   static constexpr int DROW = n + 1;                 // D rows padded: 8 rows n apart share banks
-  static constexpr int CELL_BYTES = (DTAB_OFF + (DLDS ? n * DROW * 8 : 0) + 15) / 16 * 16;
+  // linear flux: the power-form coefficients (KTab::beta) in LDS
+  static constexpr int BTAB_OFF = DTAB_OFF + (DLDS ? n * DROW * 8 : 0);
+  static constexpr int CELL_BYTES = (BTAB_OFF + (CK ? KTab<n, Real>::BK * 8 : 0) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = CPB * CELL_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "predictor LDS exceeds the CU's 160 KiB");
   // per cell; layout [face][time][qty][var][face node] (face nodes fastest:
@@ -345,6 +350,13 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   // node thread its own value): the node threads write their d fluxes of x,
   // then gather from the d pencils through their node (one barrier before,
   // one after, which frees Fs).
+  if constexpr (K::CK) {
+    if (a == 0) {
+      double* sB = reinterpret_cast<double*>(base + K::BTAB_OFF);
+#pragma unroll
+      for (int k = 0; k < KTab<n, Real>::BK; ++k) sB[k] = p.t.beta[k];
+    }
+  }
   // D (the matrix-core form: Dx) in LDS for the gathers (n >= 7)
   [[maybe_unused]] double* sDg = reinterpret_cast<double*>(base + K::DTAB_OFF);
   if constexpr (K::DLDS) {
@@ -437,34 +449,21 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     // over the n time slices.  The finalisation needs only the time average
     // qbar = sum_k (-c)^k (w . T_k) L^k u (linear fluxes: Fbar = F(qbar)).
     Real vk[M];
-    double T[n];
+    const double* sB = reinterpret_cast<const double*>(base + K::BTAB_OFF);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       vk[v] = (Real)u[v];
       qbar_ck[v] = u[v];
     }
-#pragma unroll
-    for (int t = 0; t < n; ++t) T[t] = (double)p.t.Ps[t];
     double ck = 1.0;
-    for (int k = 1; k <= p.R; ++k) {
-      if (k > 1) {
-        double Tn[n];
-#pragma unroll
-        for (int t = 0; t < n; ++t) {
-          double a2 = 0.0;
-#pragma unroll
-          for (int tt = 0; tt < n; ++tt) a2 = fma((double)p.t.P[t][tt], T[tt], a2);
-          Tn[t] = a2;
-        }
-#pragma unroll
-        for (int t = 0; t < n; ++t) T[t] = Tn[t];
-      }
+    // L^k u vanishes for k > d N in exact arithmetic (BK covers that), so
+    // iterations past BK would add only products of two rounding residues
+    const int RK = p.R < KTab<n, Real>::BK ? p.R : KTab<n, Real>::BK;
+    for (int k = 1; k <= RK; ++k) {
       Real rv[M];
       gather_L(vk, rv);
       ck *= -cdt;
-      double beta = 0.0;
-#pragma unroll
-      for (int t = 0; t < n; ++t) beta = fma(p.t.w[t], T[t], beta);
+      const double beta = sB[k - 1];   // w . T_k (written before gather_L's barriers)
 #pragma unroll
       for (int v = 0; v < M; ++v) {
         vk[v] = rv[v];
@@ -640,21 +639,19 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   __syncthreads();   // LDS is reused below
 
   // ---- extrapolate + integrateVolume on time averages (float64) ----
-  double* Fb = reinterpret_cast<double*>(base);   // [axis][var][node]: time-averaged F_i
-  double* Qb = Fb + D * NS * M;                   // [var][node]: time-averaged q
+  // [axis][var][node]: time-averaged F_i (linear flux: one axis at a time)
+  double* Fb = reinterpret_cast<double*>(base);
+  double* Qb = Fb + (K::CK ? 1 : D) * NS * M;     // [var][node]: time-averaged q
   double* Vs = Qb + NS * M;                       // [var][node]: volume term
+  [[maybe_unused]] const auto cpd = PDE::template cell<double>(p.par + cs * K::NPAR);
   if (node && K::CK) {
     if constexpr (K::CK) {
-      const auto cpd = PDE::template cell<double>(p.par + cs * K::NPAR);
 #pragma unroll
       for (int v = 0; v < M; ++v) Qb[v * NS + a] = qbar_ck[v];
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        double F[M];
-        PDE::template flux<I>(qbar_ck, F, p.gd, cpd);
+      double F[M];
+      PDE::template flux<0>(qbar_ck, F, p.gd, cpd);
 #pragma unroll
-        for (int v = 0; v < M; ++v) Fb[(I * M + v) * NS + a] = F[v];
-      });
+      for (int v = 0; v < M; ++v) Fb[v * NS + a] = F[v];
     }
   } else if (node) {
     double fb[D][M];
@@ -689,7 +686,18 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
   __syncthreads();
   static_for<0, D>([&](auto I_) {
     constexpr int I = decltype(I_)::value;
-    const double* FbI = Fb + I * M * NS;
+    if constexpr (K::CK && I > 0) {
+      // F_I(qbar) into the one flux plane (the previous axis' readers are
+      // done: barrier at the end of its tasks)
+      if (node) {
+        double F[M];
+        PDE::template flux<I>(qbar_ck, F, p.gd, cpd);
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fb[v * NS + a] = F[v];
+      }
+      __syncthreads();
+    }
+    const double* FbI = Fb + (K::CK ? 0 : I * M * NS);
     // one (variable, face node) pair per task: traces of q and F_I on both
     // faces normal to I, and the Kv contraction of F_I along the pencil
     for (int task = a; task < M * NF; task += K::TPC) {
