@@ -351,29 +351,40 @@ def run_path(st, Q0, steps, warmup, cfl, torch):
 
 
 def spacetime_workload(args, torch):
-    """The headline workload with space-time traces (Table 1's cardinalities:
-    q and F.n at every time node of every face node, a Rusanov solve per
-    time node): float64, fused and two-kernel paths, and the measured HBM
-    bytes of the corrector and predictor against their algorithmic bytes."""
+    """A workload with space-time traces (Table 1's cardinalities: q and F.n
+    at every time node of every face node, a Rusanov solve per time node):
+    fused and two-kernel paths with the float64 and the float predictor, and
+    the float64 corrector's bandwidth against its algorithmic bytes.  C2
+    takes --cells; C5 runs at its own size."""
     from paper_1801_08682_amd import inputs
     from paper_1801_08682_amd.stepper import Stepper
-    wl = inputs.preset("C2").with_(n_cells=(args.cells,) * 3, length=args.cells / 81.0)
+    name = args.workload if args.workload in ("C2", "C5") else "C2"
+    wl = inputs.preset(name)
+    if name == "C2":
+        wl = wl.with_(n_cells=(args.cells,) * 3, length=args.cells / 81.0)
     d, n, m = wl.dim, wl.n, wl.m
     Q0 = torch.tensor(inputs.initial_state(wl), device="cuda")
-    st = Stepper(wl, fused=True, spacetime=True)
-    Q, wall, sweep, reruns, _ = run_fused_path(st, Q0, args.steps, args.warmup, wl.cfl, C_DT, torch)
-    _, wall2, pred, corr, dtk = run_path(st, Q0, args.steps, args.warmup, wl.cfl, torch)
-    st.close()
     dofs = wl.ncells * wl.dofs_per_cell
-    hull = 2 * d * 2 * m * n ** d * 8                     # bytes per cell, every time node
-    return {"metric": "DoF-updates/s", "unit": "DoF-updates/s",
-            "workload": f"C2 with space-time traces ({args.cells}^3 cells, Euler N=4)",
-            "fused": {"value": dofs * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
-                      "sweep_ms": sweep, "reruns": reruns},
-            "two_kernel": {"value": dofs * args.steps / wall2, "ms_per_step": wall2 * 1e3 / args.steps,
-                           "kernel_ms": {"predict": pred, "correct": corr, "cfl_dt": dtk}},
-            "hull_bytes_per_cell": hull,
-            "correct_hbm_GBps": (2 * m * n ** d * 8 + hull) * wl.ncells / (corr * 1e-3) / 1e9}
+    out = {"metric": "DoF-updates/s", "unit": "DoF-updates/s",
+           "workload": f"{name} with space-time traces ({wl.n_cells[0]}^3 cells, Euler N={wl.order})"}
+    for key, prec, size in (("fp64", inputs.FP64, 8), ("fp32_predictor", inputs.FP32, 4)):
+        st = Stepper(wl.with_(precision=prec), fused=True, spacetime=True)
+        Q, wall, sweep, reruns, _ = run_fused_path(st, Q0, args.steps, args.warmup, wl.cfl, C_DT, torch)
+        _, wall2, pred, corr, dtk = run_path(st, Q0, args.steps, args.warmup, wl.cfl, torch)
+        st.close()
+        hull = 2 * d * 2 * m * n ** d * size              # bytes per cell, every time node
+        leg = {"fused": {"value": dofs * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
+                         "sweep_ms": sweep, "reruns": reruns},
+               "two_kernel": {"value": dofs * args.steps / wall2,
+                              "ms_per_step": wall2 * 1e3 / args.steps,
+                              "kernel_ms": {"predict": pred, "correct": corr, "cfl_dt": dtk}},
+               "hull_bytes_per_cell": hull,
+               "correct_hbm_GBps": (2 * m * n ** d * 8 + hull) * wl.ncells / (corr * 1e-3) / 1e9}
+        if key == "fp64":
+            out.update(leg)
+        else:
+            out[key] = leg
+    return out
 
 
 def run_fused_path(st, Q0, steps, warmup, cfl, c_dt, torch):
@@ -421,8 +432,8 @@ def main():
                     help="C2 is the headline line; the others print their own line "
                          "(float64 and float-predictor throughput and per-field error)")
     ap.add_argument("--traces", default="time-integrated", choices=["time-integrated", "spacetime"],
-                    help="spacetime: print one line for the headline workload with space-time "
-                         "traces and a Rusanov solve per time node")
+                    help="spacetime: print one line for C2 (or --workload C5) with space-time "
+                         "traces and a Rusanov solve per time node, float64 and float predictor")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="predictor precision of the headline line (fp64 is the metric's "
                          "float64 step; the others are for profiling the reduced-precision "
@@ -451,14 +462,14 @@ def main():
             res["copy_calib_bytes"] = copy_calibration(args, torch)
         print(json.dumps(res), flush=True)
         return
-    if args.workload != "C2":
-        print(json.dumps(other_workload(args, torch)), flush=True)
-        return
-    if args.traces == "spacetime":
+    if args.traces == "spacetime" and args.workload in ("C2", "C5"):
         res = spacetime_workload(args, torch)
         if args.copy_calib_mb:
             res["copy_calib_bytes"] = copy_calibration(args, torch)
         print(json.dumps(res), flush=True)
+        return
+    if args.workload != "C2":
+        print(json.dumps(other_workload(args, torch)), flush=True)
         return
     wl = inputs.preset("C2").with_(n_cells=(args.cells,) * 3,
                                    length=args.cells / 81.0)

@@ -84,8 +84,9 @@ typedef struct {
   int32_t spacetime_traces; /* nonzero: the hull keeps q and F.n at every time node and the
                                Riemann problems are solved per time node (Table 1's
                                extrapolate and solveRiemann cardinalities), F* integrated in
-                               time; FP64, orders up to 5, no adjoint.  0: time-integrated
-                               traces (one value per face node) */
+                               time; with the FP64 or FP32 predictor (the hull in that
+                               precision), every instantiated order; not with ADG_BF16, no
+                               adjoint.  0: time-integrated traces (one value per face node) */
 } adg_config;
 
 typedef struct adg_ctx adg_ctx;

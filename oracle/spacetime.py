@@ -8,11 +8,19 @@ face nodes and both sides of the directional speed at that time node), and
 integrateFace uses the time integral sum_t w_t F*(t).  The volume term and
 the update are those of ``step.step``.  With a constant wave speed (linear
 advection) this is the time-integrated step exactly.
+
+``step_st_mixed`` is the same step with the predictor in a reduced precision
+(``mixed.predictor_mixed``): it rounds what ``mixed.step_mixed`` rounds, and
+the hull it stores between extrapolate and solveRiemann holds every time
+node's traces in the predictor's precision.
 """
 
 import torch
 
+from . import mixed
 from . import step as ostep
+
+F64 = torch.float64
 
 
 def extrapolate_st(q, par, s):
@@ -57,6 +65,60 @@ def step_st(Q, par, dt, s):
     plus, minus = ostep.neighbor_index(s.n_cells)
     Fp, Fm = [], []
     for i in range(s.dim):
+        pi = torch.as_tensor(plus[i])
+        mi = torch.as_tensor(minus[i])
+        tr_plus = tuple(t[pi] for t in tr[i])
+        par_plus = None if par is None else par[pi]
+        F = face_fluxes_st(tr[i], tr_plus, par, par_plus, i, s)
+        Fp.append(F)
+        Fm.append(F[mi])
+    return ostep.integrate_face(Qt, Fp, Fm, dt, s).reshape(C, -1, s.m)
+
+
+def step_st_mixed(Q, par, dt, s, precision):
+    """Q(T + dt) with space-time traces and the predictor of Eq. (3) in
+    ``precision`` ("fp64", "fp32", "bf16"; see ``mixed``).
+
+    The Picard iterate q at every space-time node comes in the working
+    precision.  Its time averages (float64 sums of the rounded values; for
+    the linear PDEs Fbar_i = F_i(qbar) in float64), the volume term, the
+    extrapolation of q(t) and F_i(q(t)) to the faces at every time node (the
+    fluxes evaluated in the working precision, the projection in float64),
+    the per-time-node Rusanov solves, the face lift and the update are
+    float64; the face values are rounded to the working precision once, when
+    stored in the hull.  The linear PDEs store only the q traces and rebuild
+    the face fluxes from them in float64 with the owning cell's material."""
+    C, d = Q.shape[0], s.dim
+    u = ostep._spatial(Q, s)
+    q = mixed.predictor_mixed(u, par, dt, s, precision)
+    hull = q.dtype
+    parq = ostep._par_view(par, d + 1, C)
+    parw = None if parq is None else parq.to(hull)
+    w = torch.as_tensor(s.tab.w, dtype=F64)
+    q64 = q.to(F64)
+    qbar = ostep.project(q64, w, dim=1)
+    if s.pde.linear:
+        Fbar = [s.pde.flux(qbar, i, ostep._par_view(par, d, C)) for i in range(d)]
+    else:
+        Fbar = [ostep.project(s.pde.flux(q, i, parw).to(F64), w, dim=1) for i in range(d)]
+    Qt = ostep.integrate_volume(u, Fbar, dt, s)
+    stored = lambda x: x.to(hull).to(F64)
+    pf = ostep._par_view(par, d, C)       # over (C, n_t, face nodes.., m)
+    tr = []
+    for i in range(d):
+        dim = -(i + 2)
+        qL = stored(ostep.project(q64, s.tab.FL, dim))
+        qR = stored(ostep.project(q64, s.tab.FR, dim))
+        if s.pde.linear:
+            fL, fR = s.pde.flux(qL, i, pf), s.pde.flux(qR, i, pf)
+        else:
+            Fi = s.pde.flux(q, i, parw).to(F64)
+            fL = stored(ostep.project(Fi, s.tab.FL, dim))
+            fR = stored(ostep.project(Fi, s.tab.FR, dim))
+        tr.append((qL, qR, fL, fR))
+    plus, minus = ostep.neighbor_index(s.n_cells)
+    Fp, Fm = [], []
+    for i in range(d):
         pi = torch.as_tensor(plus[i])
         mi = torch.as_tensor(minus[i])
         tr_plus = tuple(t[pi] for t in tr[i])

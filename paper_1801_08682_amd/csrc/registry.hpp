@@ -21,12 +21,14 @@ constexpr bool bf16_instantiated() {
 
 template <template <int> class PDET, int D, int N>
 const Launchers* pick_precision(int prec, bool st) {
-  if (st) {     // space-time traces: float64, orders up to 5
-    if constexpr (N <= 5) {
-      if (prec == 0) {
-        static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, double, true>>();
-        return &L;
-      }
+  if (st) {     // space-time traces: float64 or float predictor (not the matrix-core one)
+    if (prec == 0) {
+      static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, double, true>>();
+      return &L;
+    }
+    if (prec == 1) {
+      static const Launchers L = make_fwd_launchers<Fwd<D, N, PDET, float, true>>();
+      return &L;
     }
     return nullptr;
   }

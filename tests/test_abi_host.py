@@ -168,24 +168,25 @@ def test_query_fused_workspace(L, name):
     assert extra <= wf - w <= extra + 2 * 256
 
 
-def test_query_spacetime_traces(L):
+@pytest.mark.parametrize("name", ["C2", "C5"])
+def test_query_spacetime_traces(L, name):
     """Space-time traces keep N+1 time values per face node (Table 1's
     extrapolate output, 4 d m (N+1)^d per cell for Euler) and the corrector's
-    time-integrated F* of the d lower faces; float64 and orders up to 5 only."""
-    wl = inputs.preset("C2")
-    _, _, w = _lib.query(cfg_of(wl))
-    c = cfg_of(wl)
-    c.spacetime_traces = 1
-    _, _, ws = _lib.query(c)
+    time-integrated F* (float64) of the d lower faces; with the float or
+    float64 predictor, not the matrix-core one."""
+    wl = inputs.preset(name)
     n, d, m = wl.n, wl.dim, wl.m
-    hull = wl.ncells * 4 * d * m * n ** (d - 1) * 8
-    assert wl.ncells * 4 * d * m * n ** d * 8 == n * hull
     # plus the corrector's first pass: F* of each cell's d lower faces
     fstar = wl.ncells * d * m * n ** (d - 1) * 8
-    assert abs((ws - w) - (n - 1) * hull - fstar) <= 2 * 256
-    c.precision = inputs.FP32
-    assert L.adg_query(ctypes.byref(c), None, None, None) == _lib.ADG_ERR_UNSUPPORTED
-    c = cfg_of(inputs.preset("C5"))
+    for prec, size in ((inputs.FP64, 8), (inputs.FP32, 4)):
+        _, _, w = _lib.query(cfg_of(wl, precision=prec))
+        c = cfg_of(wl, precision=prec)
+        c.spacetime_traces = 1
+        _, _, ws = _lib.query(c)
+        hull = wl.ncells * 4 * d * m * n ** (d - 1) * size
+        assert wl.ncells * 4 * d * m * n ** d * size == n * hull
+        assert abs((ws - w) - (n - 1) * hull - fstar) <= 2 * 256
+    c = cfg_of(wl, precision=inputs.BF16)
     c.spacetime_traces = 1
     assert L.adg_query(ctypes.byref(c), None, None, None) == _lib.ADG_ERR_UNSUPPORTED
 

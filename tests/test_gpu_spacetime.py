@@ -5,6 +5,7 @@ import pytest
 import torch
 
 from oracle import spacetime as ost
+from oracle import step as ostep
 from paper_1801_08682_amd import inputs
 from paper_1801_08682_amd.inputs import ACOUSTIC, ADVECTION, ELASTIC, EULER
 from tests.helpers import max_rel, setup_of
@@ -12,10 +13,9 @@ from tests.helpers import max_rel, setup_of
 pytestmark = pytest.mark.gpu
 
 
-def _wl(pde, d, N, nc):
-    h = 1.0 / 6.0
+def _wl(pde, d, N, nc, h=1.0 / 6.0, precision=inputs.FP64):
     pp = {EULER: (1.4,), ADVECTION: (1.0, -0.5, 0.3)[:d]}.get(pde, ())
-    return inputs.Workload("st", pde, d, N, nc, nc[0] * h, pp)
+    return inputs.Workload("st", pde, d, N, nc, nc[0] * h, pp, precision=precision)
 
 
 CASES = [
@@ -25,6 +25,7 @@ CASES = [
     (ACOUSTIC, 3, 2, (4, 3, 3), 1.0, 2),
     (ELASTIC, 2, 3, (5, 4), 1.0, 2),
     (ADVECTION, 2, 3, (5, 6), 1.0, 2),
+    (EULER, 3, 7, (2, 2, 2), 0.1, 1),      # the gather-form predictor (n = 8)
 ]
 
 
@@ -81,3 +82,52 @@ def test_spacetime_has_no_adjoint():
         st.step_adjoint(Q, None, st.scalar(1e-3), Q.clone())
     assert e.value.status == _lib.ADG_ERR_UNSUPPORTED
     st.close()
+
+
+FLOAT_CASES = [
+    (EULER, 3, 4, (4, 3, 3)),
+    (EULER, 3, 7, (2, 2, 2)),
+    (ELASTIC, 3, 5, (3, 2, 2)),
+    (ACOUSTIC, 3, 3, (4, 3, 3)),
+    (ADVECTION, 2, 3, (5, 6)),
+]
+
+
+@pytest.mark.parametrize("pde,d,N,nc", FLOAT_CASES)
+def test_spacetime_float_predictor_matches_emulation(pde, d, N, nc):
+    """The float predictor with space-time traces against the oracle's
+    emulation (step_st_mixed "fp32"), element by element.  The float32
+    quantities are those of the time-integrated float path, and each time
+    node's traces are rounded once when stored, as the time-averaged ones
+    are there, so the same derived bound holds: 8 u k max|Q| with u = 2^-24
+    after k steps (the float predictor's parity test gives the derivation;
+    the Rusanov flux of each time node enters with weight w_t, and the
+    weights sum to one)."""
+    from paper_1801_08682_amd.stepper import Stepper
+    steps = 2
+    wl = _wl(pde, d, N, nc, h=1.0 / 9.0, precision=inputs.FP32)
+    Q0 = inputs.random_state(wl, seed=90 + N, amplitude=0.05)
+    par = inputs.cell_params(wl, seed=91)
+    s = setup_of(wl)
+    Qt = torch.tensor(Q0)
+    pt = None if par is None else torch.tensor(par)
+    dt = ostep.cfl_dt(ostep.max_wave_speed(Qt, pt, s), 0.5 * inputs.stable_cfl(N), s)
+    print(f"space-time float parity pde={pde} d={d} N={N} grid={nc} dt={dt}", flush=True)
+    st = Stepper(wl, spacetime=True)
+    Q = torch.tensor(Q0, device="cuda")
+    p = None if par is None else torch.tensor(par, device="cuda")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dtt = st.scalar(dt)
+    for _ in range(steps):
+        st.step(Q, p, dtt, flag)
+    torch.cuda.synchronize()
+    st.close()
+    Qe = Qt
+    for _ in range(steps):
+        Qe = ost.step_st_mixed(Qe, pt, dt, s, "fp32")
+    assert int(flag.item()) == 0
+    dev = float((Q.cpu() - Qe).abs().max())
+    scale = float(Qe.abs().max())
+    print("max |gpu - emulation| / max|Q|", dev / scale, flush=True)
+    assert dev <= 8 * 2.0 ** -24 * steps * scale
+

@@ -8,6 +8,9 @@ time node (Table 1's extrapolate / solveRiemann cardinalities), CPU only.
 * A brute-force evaluation with explicit loops over cells, faces, time nodes
   and face nodes on a tiny Euler grid (the predictor and the volume term are
   taken from the oracle; they are pinned elsewhere).
+* The reduced-precision form (step_st_mixed): unrounded it is the float64
+  space-time step; in float32 a constant state stays constant, the totals
+  are conserved and the error against float64 sits at the float32 scale.
 """
 
 import numpy as np
@@ -16,9 +19,9 @@ import torch
 
 from oracle import spacetime as ost
 from oracle import step as ostep
-from oracle.diagnostics import totals
+from oracle.diagnostics import l2, totals
 from paper_1801_08682_amd import inputs
-from paper_1801_08682_amd.inputs import ADVECTION, ACOUSTIC, EULER
+from paper_1801_08682_amd.inputs import ADVECTION, ACOUSTIC, ELASTIC, EULER
 
 
 def _case(pde, d, N, nc, seed, amp):
@@ -90,3 +93,39 @@ def test_euler_brute_force():
     assert np.abs(got - ref).max() < 1e-13
     # and the per-time-node solve differs from the time-integrated one
     assert np.abs(got - ostep.step(Q, None, dt, s).numpy().reshape(C, n, n, m)).max() > 1e-9
+
+
+# The reduced-precision space-time step: pinned like the plain mixed step
+# (its unrounded arrangement is the float64 space-time step above; a constant
+# state stays constant and the totals are conserved in any precision; the
+# float32 error sits at the float32 scale).
+MIXED_CASES = [(EULER, 2, 3, (4, 3)), (ACOUSTIC, 3, 2, (3, 3, 2)), (ELASTIC, 2, 2, (3, 4))]
+
+
+def _mixed_case(pde, d, N, nc):
+    s, Q, par = _case(pde, d, N, nc, seed=5, amp=0.05 if pde == EULER else 1.0)
+    dt = ostep.cfl_dt(ostep.max_wave_speed(Q, par, s), 0.5 * inputs.stable_cfl(N), s)
+    return s, Q, par, dt
+
+
+@pytest.mark.parametrize("pde,d,N,nc", MIXED_CASES)
+def test_mixed_unrounded_arrangement_is_the_plain_st_step(pde, d, N, nc):
+    s, Q, par, dt = _mixed_case(pde, d, N, nc)
+    a = ost.step_st_mixed(Q, par, dt, s, "fp64")
+    b = ost.step_st(Q, par, dt, s)
+    assert float((l2(a - b, s) / l2(b - Q, s)).max()) < 1e-12
+
+
+@pytest.mark.parametrize("pde,d,N,nc", MIXED_CASES)
+def test_mixed_st_invariants_and_error_size(pde, d, N, nc):
+    s, Q, par, dt = _mixed_case(pde, d, N, nc)
+    c = Q[0:1, 0:1].expand_as(Q).clone()
+    pc = None if par is None else par[0:1].expand_as(par).clone()
+    out = ost.step_st_mixed(c, pc, dt, s, "fp32")
+    assert (out - c).abs().max() < 1e-13 * (1 + c.abs().max())
+    M0 = totals(Q, s)
+    out = ost.step_st_mixed(Q, par, dt, s, "fp32")
+    assert (totals(out, s) - M0).abs().max() < 1e-14 * (1 + M0.abs().max())
+    ref = ost.step_st(Q, par, dt, s)
+    e32 = float((l2(out - ref, s) / l2(ref - Q, s)).max())
+    assert 1e-9 < e32 < 256 * 2.0 ** -24
