@@ -669,6 +669,16 @@ def measured_peaks(torch):
             assert P.adg_peak_fma(prec, blocks, iters, ctypes.c_void_p(sink.data_ptr()), h) == 0
         t = best(fma)
         out[f"{name}_fma_TFLOPs"] = blocks * 256 * 16 * iters * 2 / t / 1e12
+        # the same rate with 1, 2, 3 and 4 waves per SIMD (256-thread workgroups,
+        # one to four per CU): float FMAs of two waves issue together, float64
+        # FMAs do not, so the float rate needs at least two waves with VALU work
+        by = {}
+        for w in (1, 2, 3, 4):
+            nb, it = 256 * w, 6000
+            def fma_w():
+                assert P.adg_peak_fma(prec, nb, it, ctypes.c_void_p(sink.data_ptr()), h) == 0
+            by[str(w)] = nb * 256 * 16 * it * 2 / best(fma_w, reps=3) / 1e12
+        out[f"{name}_fma_TFLOPs_by_waves_per_simd"] = by
     n = 1 << 28
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
