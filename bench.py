@@ -195,7 +195,10 @@ def c5_gradient_bench(args):
     with the device-computed dt (recorded, then held fixed in the reverse
     sweep), gradient of the final kinetic energy w.r.t. the initial density
     DoFs by the checkpointed rollout (checkpoint every 10).  float64 forward
-    and adjoint; also one adg_step_adjoint against one adg_step."""
+    and adjoint; also one adg_step_adjoint against one adg_step; then the
+    same gradient with the forward steps taken by the float and by the
+    bfloat16 (matrix-core) predictor and the float64 adjoint at their states,
+    with its distance from the float64 gradient."""
     import numpy as np
     import torch
     from paper_1801_08682_amd import inputs
@@ -242,11 +245,37 @@ def c5_gradient_bench(args):
     ev[2].record()
     torch.cuda.synchronize()
     fwd_ms, adj_ms = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+    out = {"workload": f"3D Euler N=7, 48^3 cells, {steps} steps, final kinetic energy, "
+                       f"checkpoint every {k}", "forward_s": t_fwd, "forward_plus_backward_s": t_fb,
+           "ratio": t_fb / t_fwd, "KE": float(KE.detach()), "grad_norm_rho0": float(g.norm()),
+           "step_ms": fwd_ms, "adjoint_step_ms": adj_ms, "step_ratio": adj_ms / fwd_ms}
+    # the configured form: the forward steps (and the checkpoint recomputes)
+    # with the reduced-precision predictor, the float64 adjoint at their states
+    g64 = g.detach().clone()
+    for name, prec in (("fp32_forward", inputs.FP32), ("bf16_forward", inputs.BF16)):
+        fw = Stepper(wl.with_(precision=prec))
+        Q = Q0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fw.run(Q, None, steps, cfl=wl.cfl)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        Qg = Q0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        QN, _ = rollout(st, Qg, None, steps, cfl=wl.cfl, checkpoint_every=k, forward=fw)
+        KEm = kinetic_energy(QN, 3, wl.h, w1)
+        KEm.backward()
+        torch.cuda.synchronize()
+        tfb = time.perf_counter() - t0
+        gm = Qg.grad[..., 0]
+        out[name] = {"forward_s": tf, "forward_plus_backward_s": tfb, "KE": float(KEm.detach()),
+                     "KE_rel_vs_fp64": float(KEm.detach()) / float(KE.detach()) - 1.0,
+                     "grad_rel_l2_vs_fp64": float((gm - g64).norm() / g64.norm())}
+        fw.close()
+        del Qg, QN
     st.close()
-    return {"workload": f"3D Euler N=7, 48^3 cells, {steps} steps, final kinetic energy, "
-                        f"checkpoint every {k}", "forward_s": t_fwd, "forward_plus_backward_s": t_fb,
-            "ratio": t_fb / t_fwd, "KE": float(KE.detach()), "grad_norm_rho0": float(g.norm()),
-            "step_ms": fwd_ms, "adjoint_step_ms": adj_ms, "step_ratio": adj_ms / fwd_ms}
+    return out
 
 
 def other_workload(args, torch):

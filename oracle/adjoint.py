@@ -7,10 +7,16 @@ Oracle (test infrastructure only).  The time-step sequence is held fixed
   p_h the DG polynomial of the first variable evaluated at the receiver
   (point values of the nodal basis, Sec. 3);
 * final kinetic energy  KE(Q_N) = sum_c h^d sum_a W_a |j|^2 / (2 rho).
+
+``grad_final_ke_mixed`` takes the forward steps with a reduced-precision
+predictor (``mixed.step_mixed``) and differentiates with the float64 step's
+linearisation at those states (the reverse sweep of the chain rule, one
+``step_vjp`` per step from the last to the first).
 """
 
 import torch
 
+from . import mixed
 from . import step as ostep
 from .diagnostics import basis_rows, kinetic_energy
 
@@ -67,3 +73,19 @@ def step_vjp(Q, par, dt, s, G):
     out = ostep.step(Q, p, float(dt), s)
     gs = torch.autograd.grad((out * G).sum(), [Q] + ([p] if p is not None else []))
     return gs[0], (gs[1] if p is not None else None)
+
+
+def grad_final_ke_mixed(Q0, s, dts, precision):
+    """(KE(Q_N), G_0) for the rollout Q_n = S_p(Q_{n-1}; dt_n) whose steps
+    take the predictor in ``precision`` ("fp64", "fp32", "bf16"), with
+    G_N = dKE/dQ at Q_N and G_{n-1} = (dS/dQ at Q_{n-1})^T G_n, S the float64
+    step (Euler, no materials)."""
+    states = [Q0]
+    for dt in dts:
+        states.append(mixed.step_mixed(states[-1], None, float(dt), s, precision))
+    QN = states[-1].clone().requires_grad_(True)
+    J = kinetic_energy(QN, s)
+    (G,) = torch.autograd.grad(J, [QN])
+    for n in range(len(dts), 0, -1):
+        G, _ = step_vjp(states[n - 1], None, dts[n - 1], s, G)
+    return float(J.detach()), G

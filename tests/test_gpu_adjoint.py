@@ -10,6 +10,7 @@ from paper_1801_08682_amd import inputs
 from paper_1801_08682_amd.rollout import rollout, receiver_rows, kinetic_energy
 from paper_1801_08682_amd.stepper import Stepper
 from oracle import adjoint as oadj
+from oracle import step as ostep
 from tests.helpers import setup_of
 
 pytestmark = pytest.mark.gpu
@@ -316,3 +317,57 @@ def test_rollout_receiver_misfit_fd_directions_and_coordinates():
         print("sound speed", int(f), "fd", fd, "adjoint", an)
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * gcm)
     st.close()
+
+
+@pytest.mark.parametrize("order,cells,prec", [
+    (3, (4, 4, 4), inputs.FP32),
+    (3, (4, 4, 4), inputs.BF16),
+    (7, (2, 2, 1), inputs.BF16),      # C5's order with the matrix-core predictor
+])
+def test_rollout_final_kinetic_energy_reduced_precision_forward(order, cells, prec):
+    """C5 with its reduced-precision predictor: the forward steps (and the
+    checkpoint recomputes) run with the float or bfloat16 predictor, and the
+    float64 adjoint steps are applied at those states, so the gradient is the
+    float64 linearisation of the step along the reduced-precision trajectory.
+    Against the oracle's grad_final_ke_mixed (its mixed step and float64 step
+    VJPs at the emulated states), 6 steps at a fixed dt, checkpoint every 4.
+    Bars: the final KE within 8 u k of the emulation's (u = 2^-24, k steps:
+    the float predictor's derived per-step state bound); the gradient's
+    relative L2 distance from the emulation's within that same 8 u k for the
+    float predictor (the reverse sweep maps a relative state change to a
+    relative gradient change of the same order over these steps), and for
+    bfloat16 within a tenth of the emulation's own distance from the float64
+    gradient, so the GPU gradient follows the bfloat16 trajectory, not the
+    float64 one."""
+    wl = inputs.preset("C5").with_(order=order, n_cells=cells, length=cells[0] / 48)
+    Q0 = inputs.initial_state(wl, seed=0)
+    s = setup_of(wl)
+    Qt = torch.tensor(Q0)
+    dt = ostep.cfl_dt(ostep.max_wave_speed(Qt, None, s), wl.cfl, s)
+    steps, k = 6, 4
+    name = {inputs.FP32: "fp32", inputs.BF16: "bf16"}[prec]
+    print(f"case reduced-precision forward KE gradient N={order} cells={cells} {name}", flush=True)
+    st = Stepper(wl, adjoint=True)
+    fw = Stepper(wl.with_(precision=prec))
+    z, om = np.polynomial.legendre.leggauss(wl.n)
+    w1 = torch.tensor(0.5 * om, device="cuda")
+    Qg = torch.tensor(Q0, device="cuda", requires_grad=True)
+    QN, _ = rollout(st, Qg, None, steps, dt=dt, checkpoint_every=k, forward=fw)
+    KE = kinetic_energy(QN, 3, wl.h, w1)
+    KE.backward()
+    g = Qg.grad[..., 0].detach().cpu()
+    st.close()
+    fw.close()
+    Je, ge = oadj.grad_final_ke_mixed(Qt, s, [dt] * steps, name)
+    J64, g64 = oadj.grad_final_ke(Qt, s, [dt] * steps)
+    ge, g64 = ge[..., 0], g64[..., 0]
+    d_ge = float((g - ge).norm() / ge.norm())
+    d_e64 = float((ge - g64).norm() / g64.norm())
+    print("KE gpu", float(KE), "emulation", Je, "float64", J64,
+          "| gradient rel L2: gpu vs emulation", d_ge, "emulation vs float64", d_e64, flush=True)
+    bar = 8 * 2.0 ** -24 * steps
+    assert abs(float(KE) - Je) <= bar * abs(Je)
+    if prec == inputs.FP32:
+        assert d_ge <= bar
+    else:
+        assert d_ge <= 0.1 * d_e64

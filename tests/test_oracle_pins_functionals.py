@@ -175,3 +175,27 @@ def test_oracle_gradients_match_central_differences():
         fd = (ke(Q0 + eps * v) - ke(Q0 - eps * v)) / (2 * eps)
         an = float((g * v).sum())
         assert abs(fd - an) <= 1e-6 * abs(an) + 1e-12
+
+
+def test_gradient_along_reduced_precision_trajectory():
+    """grad_final_ke_mixed: unrounded ("fp64") it is autograd through the
+    whole float64 rollout (so its reverse sweep takes the states and steps in
+    the right order); with the float predictor the states, and so the
+    gradient, move at the float scale only."""
+    from oracle import mixed
+    from oracle.adjoint import grad_final_ke, grad_final_ke_mixed
+    wl = inputs.Workload("k", inputs.EULER, 3, 2, (2, 2, 1), 1.0, (1.4,))
+    s = ostep.Setup(EULER, 3, 2, (2, 2, 1), 0.5, (1.4,))
+    Q0 = torch.tensor(inputs.random_state(wl, seed=6, amplitude=0.2))
+    dts = [0.01, 0.012, 0.011]
+    KE, g = grad_final_ke(Q0, s, dts)
+    KE64, g64 = grad_final_ke_mixed(Q0, s, dts, "fp64")
+    assert abs(KE64 - KE) <= 1e-13 * abs(KE)
+    assert float((g64 - g).norm() / g.norm()) < 1e-12
+    KE32, g32 = grad_final_ke_mixed(Q0, s, dts, "fp32")
+    Q = Q0
+    for dt in dts:
+        Q = mixed.step_mixed(Q, None, dt, s, "fp32")
+    assert KE32 == float(kinetic_energy(Q, s))
+    rel = float((g32 - g).norm() / g.norm())
+    assert 1e-12 < rel < 1e-4
