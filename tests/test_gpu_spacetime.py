@@ -55,11 +55,19 @@ def test_spacetime_matches_oracle(pde, d, N, nc, amp, steps):
     assert max_rel(Q.cpu(), QO, wl) < 1e-12
 
 
-def test_spacetime_fused_matches_plain():
+@pytest.mark.parametrize("N,nc,prec", [
+    (3, (4, 4, 3), inputs.FP64),
+    (3, (4, 4, 3), inputs.FP32),
+    (7, (2, 2, 2), inputs.FP64),
+])
+def test_spacetime_fused_matches_plain(N, nc, prec):
     """The fused sweep with space-time traces equals plain steps with the
-    recorded dts (both on the GPU; the plain path is checked above)."""
+    recorded dts (both on the GPU; the plain path is checked above): the
+    same predictor, and the fused corrector's one-pass face solve takes the
+    two-pass corrector's operands in the same order."""
     from paper_1801_08682_amd.stepper import Stepper
-    wl = _wl(EULER, 3, 3, (4, 4, 3))
+    wl = _wl(EULER, 3, N, nc, precision=prec)
+    print(f"space-time fused vs plain N={N} grid={nc} precision={prec}", flush=True)
     Q0 = torch.tensor(inputs.random_state(wl, seed=9, amplitude=0.2), device="cuda")
     st = Stepper(wl, fused=True, spacetime=True)
     Q = Q0.clone()
