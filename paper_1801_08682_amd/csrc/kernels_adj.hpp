@@ -841,6 +841,9 @@ __global__ void __launch_bounds__(K::NODE_THREADS) __attribute__((amdgpu_waves_p
   using PDE = typename K::PDE;
   constexpr int n = K::n, M = K::M, NS = K::NS, NF = K::NF, D = K::D, NPAR = K::NPAR;
   constexpr int CPB = K::CPB, NSP = K::NSP, RR = K::N + 1;
+  // the gathers use the first of D plane slots: the one-plane layout (a
+  // third of the LDS, six workgroups per CU instead of five for C4)
+  // measured slower
   constexpr int CELLD = D * NSP * K::MP;                  // doubles of LDS per cell
   // z_1..z_R of the material terms in LDS when they fit beside the gather
   // planes, else in the block's scratch slot
@@ -853,7 +856,7 @@ __global__ void __launch_bounds__(K::NODE_THREADS) __attribute__((amdgpu_waves_p
   double* pred = smem;
   const int lc = threadIdx.x / NS;
   const int a = threadIdx.x - lc * NS;
-  double* Fs = smem + lc * CELLD;                          // [axis][var][node] planes
+  double* Fs = smem + lc * CELLD;                          // [var][node] plane (slots of plane 0)
   const double c = (*p.dt) * p.inv_h;
   for (int i = threadIdx.x; i < n * n; i += K::NODE_THREADS) s_D[i / n][i % n] = p.t.D[i / n][i % n];
   if (threadIdx.x == 0) {
@@ -884,17 +887,14 @@ __global__ void __launch_bounds__(K::NODE_THREADS) __attribute__((amdgpu_waves_p
 #pragma unroll
     for (int k = 0; k < (NPAR > 0 ? NPAR : 1); ++k) pb[k] = 0.0;
 
-    // z <- a_k u + L z (every node thread gives its z)
+    // z <- a_k u + L z (every node thread gives its z).  F_i(z) = A_i z with
+    // the cell's constant material, so L z = sum_i A_i (D_i z): one plane of
+    // z, gathered along the d pencils, the flux of each axis at the node.
     double z[M];
     auto horner = [&](int k) {
       __syncthreads();                                    // earlier readers of Fs done
-      static_for<0, D>([&](auto I_) {
-        constexpr int I = decltype(I_)::value;
-        double F[M];
-        PDE::template flux<I>(z, F, p.g, cp);
 #pragma unroll
-        for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(I * NSP + K::slot(a), v)] = F[v];
-      });
+      for (int v = 0; v < M; ++v) Fs[K::template lidx_e<D>(K::slot(a), v)] = z[v];
       __syncthreads();
       const double ak = s_al[k];
 #pragma unroll
@@ -902,15 +902,20 @@ __global__ void __launch_bounds__(K::NODE_THREADS) __attribute__((amdgpu_waves_p
       static_for<0, D>([&](auto I_) {
         constexpr int I = decltype(I_)::value;
         constexpr int sI = K::sstride(I);
-        __builtin_amdgcn_sched_barrier(0);               // one pencil's loads live at a time
         const int ai = coord<n, I>(a);
-        const int e0 = I * NSP + K::slot(a) - ai * sI;
+        const int e0 = K::slot(a) - ai * sI;
+        double dr[n], g[M], F[M];
 #pragma unroll
-        for (int j = 0; j < n; ++j) {
-          const double dj = s_D[ai][j];
+        for (int j = 0; j < n; ++j) dr[j] = s_D[ai][j];
 #pragma unroll
-          for (int v = 0; v < M; ++v) z[v] = fma(dj, Fs[K::template lidx_e<D>(e0 + j * sI, v)], z[v]);
+        for (int v = 0; v < M; ++v) {
+          g[v] = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) g[v] = fma(dr[j], Fs[K::template lidx_e<D>(e0 + j * sI, v)], g[v]);
         }
+        PDE::template flux<I>(g, F, p.g, cp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) z[v] += F[v];
       });
     };
     // zb <- L^T zb with the state zk of the material terms; u bar += a_k zb first

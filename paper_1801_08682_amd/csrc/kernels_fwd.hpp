@@ -428,6 +428,50 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     });
     __syncthreads();                                // Fs is reused after
   };
+  // Linear flux: F_i(q) = A_i q with the cell's constant material, so
+  // sum_i D_i F_i(x) = sum_i A_i (D_i x): one plane of x in LDS, gathered
+  // along the d pencils through the node, then the flux of each axis applied
+  // to its gathered derivative at the node (a third of the LDS writes of
+  // gather_L).  float: the derivative of x - x_node (D's rows sum to zero),
+  // so a constant field has exactly zero derivative.
+  [[maybe_unused]] auto gather_Lx = [&](const Real (&x)[M], Real (&rv)[M]) {
+    Real* Xs = reinterpret_cast<Real*>(base);      // [var][node] plane
+    constexpr bool REF = !std::is_same<Real, double>::value;
+    if (node) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) Xs[K::template lidx_e<1>(K::slot(pa), v)] = x[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < M; ++v) rv[v] = Real(0);
+    if (node) static_for<0, D>([&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      constexpr int sI = K::sstride(I);
+      const int ai = coord<n, I>(pa);
+      const int e0 = K::slot(pa) - ai * sI;
+      Real g[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) g[v] = Real(0);
+      // variable by variable: the pencil's n m loads are not all in flight
+      // (and live) at once
+      Real dr[n];
+#pragma unroll
+      for (int j = 0; j < n; ++j) dr[j] = K::DLDS ? (Real)sDg[ai * K::DROW + j] : p.t.D[ai][j];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          const Real xv = Xs[K::template lidx_e<1>(e0 + j * sI, v)];
+          g[v] = fma(dr[j], REF ? xv - x[v] : xv, g[v]);
+        }
+      }
+      Real F[M];
+      PDE::template flux<I>(g, F, p.g, cp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) rv[v] += F[v];
+    });
+    __syncthreads();                                // Xs is reused after
+  };
   auto first_iteration = [&]() {
     Real uu[M], rv[M];
 #pragma unroll
@@ -461,9 +505,9 @@ __device__ __forceinline__ void pred_cell(const PredP<K>& p, unsigned char* base
     const int RK = p.R < KTab<n, Real>::BK ? p.R : KTab<n, Real>::BK;
     for (int k = 1; k <= RK; ++k) {
       Real rv[M];
-      gather_L(vk, rv);
+      gather_Lx(vk, rv);
       ck *= -cdt;
-      const double beta = sB[k - 1];   // w . T_k (written before gather_L's barriers)
+      const double beta = sB[k - 1];   // w . T_k (written before gather_Lx's barriers)
 #pragma unroll
       for (int v = 0; v < M; ++v) {
         vk[v] = rv[v];
